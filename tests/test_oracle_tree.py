@@ -1,0 +1,248 @@
+"""Pins of the oracle's Morton keys, octree, cell moments and walk.
+
+Checks use hand-placed points, brute-force re-derivations from the keys,
+conservation of mass and particles, and the theta = 0 identity with the
+direct sum.
+"""
+import numpy as np
+import pytest
+
+import synth
+
+ONE21 = (1 << 21) - 1
+
+
+def test_interleave_hand_values(orc):
+    # x is the most significant of each 3-bit digit
+    assert orc.interleave(1, 0, 0) == 4
+    assert orc.interleave(0, 1, 0) == 2
+    assert orc.interleave(0, 0, 1) == 1
+    assert orc.interleave(2, 0, 0) == 32
+    assert orc.interleave(1 << 20, 0, 0) == 1 << 62
+    assert orc.interleave(ONE21, ONE21, ONE21) == (1 << 63) - 1
+    # x = 011, y = 101, z = 110: digits (bit2) 011, (bit1) 101, (bit0) 110
+    assert orc.interleave(3, 5, 6) == 0b011_101_110
+
+
+def test_keys_of_hand_placed_points(orc):
+    # lo = (0,0,0), extent 1 -> side 1, q = floor(u * 2^21) clamped to 2^21 - 1
+    x = np.array([[1.0, 0.0, 0.5, 0.25],
+                  [1.0, 0.0, 0.0, 0.5],
+                  [1.0, 0.0, 0.0, 0.75]])
+    m = np.ones(4)
+    T = orc.Tree(x, m, n_crit=2, theta=0.5)
+    lo, side = T.frame()
+    assert np.all(lo == 0.0) and side == 1.0
+    perm, key, u = T.sorted()
+    # q: p0 = (ONE21,)*3 ; p1 = 0 ; p2 = (2^20, 0, 0) ; p3 = (2^19, 2^20, 3*2^19)
+    k0 = (1 << 63) - 1
+    k2 = 1 << 62
+    # p3: q = (2^19, 2^20, 2^20 + 2^19); bit 20: x=0,y=1,z=1 -> 011 ;
+    # bit 19: x=1,y=0,z=1 -> 101 ; lower bits 0
+    k3 = (0b011 << 60) | (0b101 << 57)
+    assert list(perm) == [1, 3, 2, 0]
+    assert list(key) == [0, k3, k2, k0]
+
+
+def test_side_is_power_of_two_cover(orc):
+    x, v, m = synth.plummer(3000, 5)
+    T = orc.Tree(x, m)
+    lo, side = T.frame()
+    ext = (x - lo[:, None]).max()
+    assert side >= ext and side / 2 < ext
+    assert np.all(lo == x.min(axis=1))
+    assert float(np.log2(side)).is_integer()
+
+
+def _brute_nodes(key, n_crit):
+    """(level, first, count) of every cell whose parent holds >= n_crit particles."""
+    key = np.asarray(key, dtype=np.uint64)
+    n = key.size
+    out = {(0, 0, n)}
+    frontier = [(0, 0, n)]
+    while frontier:
+        nxt = []
+        for lev, b, c in frontier:
+            if c < n_crit or lev == 21:
+                continue
+            sh = np.uint64(3 * (21 - (lev + 1)))
+            pref = key[b:b + c] >> sh
+            vals, starts, counts = np.unique(pref, return_index=True, return_counts=True)
+            for s0, c0 in zip(starts, counts):
+                node = (lev + 1, b + int(s0), int(c0))
+                out.add(node)
+                nxt.append(node)
+        frontier = nxt
+    return out
+
+
+@pytest.mark.parametrize("n,n_crit,seed", [(1, 16, 1), (15, 16, 1), (16, 16, 1), (256, 16, 2),
+                                           (200, 1, 3), (256, 4, 4)])
+def test_octree_vs_bruteforce(orc, n, n_crit, seed):
+    x, v, m = synth.plummer(n, seed)
+    T = orc.Tree(x, m, n_crit=n_crit)
+    perm, key, u = T.sorted()
+    nd = T.nodes()
+    got = set(zip(nd["level"].tolist(), nd["first"].tolist(), nd["count"].tolist()))
+    assert got == _brute_nodes(key, n_crit)
+    assert len(got) == T.nnodes
+
+
+def test_octree_invariants(orc):
+    x, v, m = synth.plummer(20000, 9)
+    # duplicate a few particles exactly to force depth-21 leaves
+    x[:, 100:140] = x[:, 99:100]
+    T = orc.Tree(x, m, n_crit=16)
+    perm, key, u = T.sorted()
+    assert np.all(np.diff(key.astype(np.float64)) >= 0)
+    assert sorted(perm.tolist()) == list(range(x.shape[1]))
+    nd = T.nodes()
+    leaf = nd["nchild"] == 0
+    # every particle sits in exactly one leaf
+    cover = np.zeros(x.shape[1], np.int64)
+    for f, c in zip(nd["first"][leaf], nd["count"][leaf]):
+        cover[f:f + c] += 1
+    assert np.all(cover == 1)
+    # leaves are small unless at the deepest level; internal nodes are not
+    assert np.all((nd["count"][leaf] < 16) | (nd["level"][leaf] == 21))
+    assert np.any(nd["level"][leaf] == 21)
+    assert np.all(nd["count"][~leaf] >= 16)
+    # children partition their parent
+    for k in np.nonzero(~leaf)[0]:
+        ch = np.nonzero(nd["parent"] == k)[0]
+        assert nd["count"][ch].sum() == nd["count"][k]
+        assert np.all(np.diff(nd["first"][ch]) > 0)
+        assert nd["first"][ch[0]] == nd["first"][k]
+
+
+def test_moments_and_geometry(orc):
+    x, v, m = synth.plummer(20000, 12)
+    m = m * np.linspace(0.5, 1.5, m.size)
+    T = orc.Tree(x, m, n_crit=8, theta=0.7)
+    lo, side = T.frame()
+    perm, key, u = T.sorted()
+    nd = T.nodes()
+    assert nd["M"][0] == pytest.approx(m.sum(), rel=1e-15)
+    com = ((x - lo[:, None]) * m).sum(axis=1) / m.sum()
+    np.testing.assert_allclose(nd["com"][:, 0], com, rtol=1e-12, atol=1e-13 * side)
+    # every particle lies in its leaf's closed box; every COM in its cell's box
+    leaf = nd["nchild"] == 0
+    for k in np.nonzero(leaf)[0][::7]:
+        f, c = nd["first"][k], nd["count"][k]
+        b = nd["blo"][:, k][:, None]
+        assert np.all(u[:, f:f + c] >= b) and np.all(u[:, f:f + c] <= b + nd["l"][k])
+    assert np.all(nd["com"] >= nd["blo"]) and np.all(nd["com"] <= nd["blo"] + nd["l"])
+    # cell side halves per level; opening radius r_b = l / theta
+    np.testing.assert_array_equal(nd["l"], side * 2.0 ** -nd["level"].astype(np.float64))
+    np.testing.assert_allclose(nd["rb2"], (nd["l"] / 0.7) ** 2, rtol=1e-15)
+    # internal mass equals the mass of its particle range
+    cm = np.concatenate([[0.0], np.cumsum(m[perm])])
+    np.testing.assert_allclose(nd["M"], cm[nd["first"] + nd["count"]] - cm[nd["first"]],
+                               rtol=1e-12, atol=1e-14 * m.sum())
+
+
+def _brute_lists(T, g, k, R2, hybrid):
+    """Accept/near sets derived node by node: a cell is on the list iff it is
+    accepted (or a leaf) while every proper ancestor was opened."""
+    nd = T.nodes()
+    perm, key, u = T.sorted()
+    b, e = k * g, min((k + 1) * g, T.n)
+    glo, ghi = u[:, b:e].min(axis=1), u[:, b:e].max(axis=1)
+
+    def dist2(lo, hi):
+        gap = np.maximum(np.maximum(glo - hi, lo - ghi), 0.0)
+        return gap[0] ** 2 + gap[1] ** 2 + gap[2] ** 2
+
+    nn = T.nnodes
+    status = []
+    for c in range(nn):
+        D1 = dist2(nd["com"][:, c], nd["com"][:, c])
+        D2 = dist2(nd["blo"][:, c], nd["blo"][:, c] + nd["l"][c])
+        sep = D2 >= R2 * R2 if hybrid else D2 > 0
+        if D1 >= nd["rb2"][c] and sep:
+            status.append("pc")
+        elif nd["nchild"][c] == 0:
+            status.append("near" if hybrid and D2 < R2 * R2 else "far")
+        else:
+            status.append("open")
+    out = {"pc": set(), "far": set(), "near": set()}
+    for c in range(nn):
+        if status[c] == "open":
+            continue
+        p, ok = nd["parent"][c], True
+        while p >= 0:
+            ok &= status[p] == "open"
+            p = nd["parent"][p]
+        if ok:
+            out[status[c]].add(c)
+    return out
+
+
+@pytest.mark.parametrize("hybrid", [0, 1])
+def test_walk_vs_bruteforce(orc, hybrid):
+    x, v, m = synth.plummer(512, 21)
+    T = orc.Tree(x, m, n_crit=8, theta=0.6)
+    for k in range(0, 512 // 32):
+        pc, far, near = T.walk_group(32, k, 0.25, hybrid)
+        ref = _brute_lists(T, 32, k, 0.25, hybrid)
+        assert set(pc.tolist()) == ref["pc"]
+        assert set(far.tolist()) == ref["far"]
+        assert set(near.tolist()) == ref["near"]
+
+
+@pytest.mark.parametrize("hybrid", [0, 1])
+def test_walk_coverage(orc, hybrid):
+    x, v, m = synth.plummer(8192, 22)
+    T = orc.Tree(x, m, n_crit=16, theta=0.5)
+    nd = T.nodes()
+    for k in range(0, 8192 // 64, 5):
+        pc, far, near = T.walk_group(64, k, 0.2, hybrid)
+        tot = nd["count"][pc].sum() + nd["count"][far].sum() + nd["count"][near].sum()
+        assert tot == 8192
+        assert nd["M"][pc].sum() + nd["M"][far].sum() + nd["M"][near].sum() == \
+            pytest.approx(m.sum(), rel=1e-13)
+    npc, nfar, nnear = T.walk_counts(64, 0.2, hybrid)
+    if not hybrid:
+        assert np.all(nnear == 0)
+
+
+def test_list_length_decreases_with_theta(orc):
+    x, v, m = synth.plummer(8192, 23)
+    tot = []
+    for th in (0.3, 0.5, 0.8):
+        T = orc.Tree(x, m, n_crit=16, theta=th)
+        c = T.walk_counts(64, 0.1, 1)
+        tot.append(c[0] + c[1] + c[2])
+    assert np.all(tot[1] <= tot[0]) and np.all(tot[2] <= tot[1])
+
+
+@pytest.mark.parametrize("hybrid", [0, 1])
+def test_theta_zero_equals_direct(orc, hybrid):
+    x, v, m = synth.plummer(4096, 1)
+    wl = synth.WORKLOADS["plummer4k"]
+    T = orc.Tree(x, m, n_crit=16, theta=0.0)
+    acc, pot, inter = T.soft(64, 1.0, wl.eps, wl.R1, wl.R2, hybrid, potential=True)
+    assert inter == 4096 * 4096
+    if hybrid:
+        _, ref, _ = orc.split_direct(x, m, 1.0, wl.eps, wl.R1, wl.R2)
+    else:
+        ref = orc.direct(x, m, 1.0, wl.eps)
+    scale = np.linalg.norm(ref, axis=0).max()
+    assert np.abs(acc - ref).max() < 1e-12 * scale
+    _, pref = orc.direct(x, m, 1.0, wl.eps, potential=True)
+    assert np.abs(pot - pref).max() < 1e-12 * np.abs(pref).max()
+
+
+def test_tree_force_error_reported(orc):
+    """theta = 0.5 tree force vs direct: the paper prints no error to pin this
+    to (parity unpinned); only a loose sanity bound is asserted."""
+    x, v, m = synth.plummer(4096, 1)
+    wl = synth.WORKLOADS["plummer4k"]
+    ref = orc.direct(x, m, 1.0, wl.eps)
+    ah, _, _ = orc.split_direct(x, m, 1.0, wl.eps, wl.R1, wl.R2, soft=False)
+    for hybrid in (0, 1):
+        T = orc.Tree(x, m, n_crit=16, theta=0.5)
+        acc, _, _ = T.soft(64, 1.0, wl.eps, wl.R1, wl.R2, hybrid)
+        tot = acc + (ah if hybrid else 0.0)
+        e = np.linalg.norm(tot - ref, axis=0) / np.linalg.norm(ref, axis=0)
+        assert np.percentile(e, 99) < 1e-2
