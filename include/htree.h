@@ -1,0 +1,178 @@
+/*
+ * htree.h -- C ABI of the MI355X (gfx950) library for the force path of the
+ * hybrid hard/soft tree method (Watanabe & Nakasato, arXiv:1406.6158).
+ *
+ * The method (section II):
+ *   - softened gravity, eq. (2): the acceleration of sink i from source j is
+ *     G m_j (r_j - r_i) / (|r_j - r_i|^2 + eps^2)^{3/2}, j != i;
+ *   - the force is split by the changeover K(r) of eq. (10) into a hard part
+ *     F K (neighbours inside R2) and a soft part F (1 - K), eqs. (7)-(9);
+ *   - the soft part comes from a Barnes-Hut octree walk (section II.B, with
+ *     grouped sinks as in section III.A.2), the hard part from a neighbour
+ *     search within R2 and a direct K-weighted sum;
+ *   - a leapfrog (section II.A eqs. 3-4) applies the hard force every
+ *     substep dt_h and the soft force every dt_s = n dt_h (section II.C).
+ *
+ * Conventions shared by every entry point:
+ *   - All pointers named d_* are DEVICE pointers on the device that is
+ *     current when htree_create is called.  Positions are float64,
+ *     velocities, masses and accelerations float32, all structure-of-arrays:
+ *     component a of particle i is at [a*n + i].  Arrays the caller passes are
+ *     in the caller's particle order; the library keeps its own
+ *     Morton-sorted copy and translates.
+ *   - The caller owns every device buffer, including the one workspace the
+ *     library carves its internal arrays from.  The library never allocates or
+ *     frees device memory; it owns only the small host-side context.
+ *   - Every call that launches work is asynchronous on the HIP stream given
+ *     to htree_create and returns once the work is enqueued.  Host-detectable
+ *     errors are returned at once; conditions found on the device are kept in
+ *     a sticky status word that htree_sync returns.
+ *   - A context is not thread-safe.  Separate contexts on separate streams
+ *     may be used concurrently.
+ *   - On error, htree_last_error() returns a text for the calling thread.
+ */
+#ifndef HTREE_H
+#define HTREE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t htree_status;
+#define HTREE_OK         0
+#define HTREE_EINVAL    (-1)  /* bad parameter or shape, or non-finite input      */
+#define HTREE_ENOMEM    (-2)  /* workspace smaller than htree_workspace_bytes     */
+#define HTREE_EDEVICE   (-3)  /* HIP runtime error (text in htree_last_error)     */
+#define HTREE_EOVERFLOW (-4)  /* a device-side capacity was exceeded              */
+#define HTREE_ESTATE    (-5)  /* call order: e.g. soft_force before build_tree    */
+
+/* htree_params.flags */
+#define HTREE_F_POT     1     /* soft_force also evaluates the tree potential     */
+#define HTREE_F_TIMING  2     /* record per-phase times with HIP events           */
+
+typedef struct {
+    double  G;            /* gravitational constant (> 0)                            */
+    double  eps;          /* Plummer softening length (> 0)                          */
+    double  theta;        /* opening angle: a cell of side l is opened while the     */
+                          /* group lies closer than l/theta; 0 opens every cell     */
+    double  R1, R2;       /* changeover band, 0 < R1 < R2 (hybrid mode only)         */
+    double  dt_soft;      /* soft timestep dt_s                                      */
+    int32_t n_sub;        /* hard substeps per soft step, dt_h = dt_s / n_sub (>= 1) */
+    int32_t hybrid;       /* 1: hard/soft split; 0: plain tree (normal-tree mode)    */
+    int32_t n_crit;       /* a cell splits while it holds >= n_crit particles (>= 1) */
+    int32_t group_size;   /* sinks sharing one walk: 64 (one wavefront)              */
+    int32_t precision;    /* 0: FP32 interactions with compensated tile sums         */
+    int32_t flags;        /* HTREE_F_*                                               */
+} htree_params;
+
+typedef struct {
+    int64_t n, n_groups, n_nodes, n_leaves;
+    int64_t soft_cells;         /* particle-cell entries, summed over groups        */
+    int64_t soft_far;           /* far particle entries, summed over groups         */
+    int64_t soft_near;          /* near (1-K weighted) particle entries             */
+    int64_t soft_interactions;  /* sum over groups of sinks x entries               */
+    int64_t hard_candidates;    /* sink-source pairs tested against R2              */
+    int64_t hard_pairs;         /* accepted neighbour pairs (sum of ngb)            */
+    float   ms_build, ms_soft, ms_hard, ms_kick;  /* last call, with HTREE_F_TIMING */
+} htree_counters;
+
+typedef struct htree_ctx htree_ctx;
+
+/* Defaults: G = 1, eps = 0.01, theta = 0.5, R1 = 0.05, R2 = 0.1, dt_soft = 1/16,
+ * n_sub = 4, hybrid = 1, n_crit = 16, group_size = 64, precision = 0, flags = 0. */
+void htree_default_params(htree_params *p);
+
+/* Exact number of workspace bytes a context for n particles needs (0 if the
+ * parameters are invalid).  This is the device footprint used for admission. */
+size_t htree_workspace_bytes(const htree_params *p, int64_t n);
+
+/* Creates a context for n >= 1 particles.  d_workspace must hold ws_bytes >=
+ * htree_workspace_bytes(p, n) bytes, 256-byte aligned, and stay valid until
+ * htree_destroy.  hip_stream is a hipStream_t (NULL: the null stream).
+ * Errors: EINVAL (params), ENOMEM (workspace too small), EDEVICE. */
+htree_status htree_create(htree_ctx **ctx, const htree_params *p, int64_t n,
+                          void *d_workspace, size_t ws_bytes, void *hip_stream);
+
+/* Copies the particle state in.  d_x [3][n] float64, d_v [3][n] float32 (may be
+ * NULL: zero velocities), d_m [n] float32.  Invalidates the tree and forces. */
+htree_status htree_set_state(htree_ctx *ctx, const double *d_x, const float *d_v,
+                             const float *d_m);
+
+/* Builds the octree of the current positions (section III.A.1): bounding box,
+ * 63-bit Morton keys in the power-of-two root cube, stable radix sort,
+ * recursive split while a cell holds >= n_crit particles, centres of mass in
+ * FP64 and opening radii.  Reorders the internal state into key order. */
+htree_status htree_build_tree(htree_ctx *ctx);
+
+/* Soft force (hybrid) or full tree force (plain) at the positions of the last
+ * build (section II.B traversal, section II.C split).  The result is kept
+ * for the integrator and, if d_acc is not NULL, written in caller order
+ * ([3][n] float32).  d_pot (float32 [n], may be NULL) receives the tree
+ * potential when the context has HTREE_F_POT.  ESTATE without a current tree. */
+htree_status htree_soft_force(htree_ctx *ctx, float *d_acc, float *d_pot);
+
+/* Hard force, section II.C: for every sink the exact neighbour set
+ * { j != i : |x_j - x_i|^2 < R2^2 } (FP64 test) and the sum of K(r) F_ij.
+ * Kept for the integrator; written in caller order if d_acc / d_ngb (int32
+ * neighbour counts) are not NULL.  ESTATE without a current tree; EINVAL in
+ * plain mode. */
+htree_status htree_hard_force(htree_ctx *ctx, float *d_acc, int32_t *d_ngb);
+
+/* Leapfrog update, section II.A eqs. (3)-(4): v += dt_kick * a, then
+ * x += dt_drift * v (FP64 positions).  d_acc is [3][n] float32 in caller
+ * order; NULL means the sum of the kept soft and hard accelerations.  A
+ * non-zero dt_drift invalidates the tree. */
+htree_status htree_kick_drift(htree_ctx *ctx, double dt_kick, const float *d_acc,
+                              double dt_drift);
+
+/* Advances n_soft_steps soft steps with the nested kick-drift-kick of
+ * section II.C (one soft-step plus n_sub - 1 hard-steps per dt_s): per soft
+ * step v += dt_s/2 a_s; n_sub times { v += dt_h/2 a_h; x += dt_h v; rebuild;
+ * last substep: a_s = soft, a_h = hard, else a_h = hard; v += dt_h/2 a_h };
+ * v += dt_s/2 a_s.  Plain mode: n_sub = 1 with the full tree force.  Forces at
+ * the initial positions are computed on the first call. */
+htree_status htree_step(htree_ctx *ctx, int32_t n_soft_steps);
+
+/* Copies positions / velocities out in caller order (either may be NULL). */
+htree_status htree_get_state(htree_ctx *ctx, double *d_x, float *d_v);
+
+/* Waits for the context's stream and returns the sticky device status
+ * (HTREE_OK, or EINVAL for non-finite input, EOVERFLOW). */
+htree_status htree_sync(htree_ctx *ctx);
+
+/* Counters of the last build / force calls.  Synchronises the stream. */
+htree_status htree_stats(htree_ctx *ctx, htree_counters *out);
+
+/* Per-group list sizes of the last soft_force: cells, far and near particle
+ * entries (host arrays of htree_counters.n_groups int32 each; any may be NULL).
+ * Synchronises the stream. */
+htree_status htree_group_counts(htree_ctx *ctx, int32_t *n_cells, int32_t *n_far,
+                                int32_t *n_near);
+
+/* Copies the sorted keys, the permutation (sorted position -> caller index)
+ * and the build frame (lo[3], side) of the last build to host memory (any
+ * pointer may be NULL).  Synchronises the stream. */
+htree_status htree_export_keys(htree_ctx *ctx, uint64_t *keys, int32_t *perm,
+                               double *frame4);
+
+/* Number of tree nodes of the last build, and their records in level order
+ * (host arrays of that length; any pointer may be NULL): level, first
+ * particle (sorted position), particle count, mass, centre of mass [3][nn]
+ * (build frame).  Synchronises the stream. */
+int64_t htree_node_count(htree_ctx *ctx);
+htree_status htree_export_nodes(htree_ctx *ctx, int32_t *level, int32_t *first,
+                                int32_t *count, double *mass, double *com);
+
+const char *htree_last_error(void);
+
+/* Releases the host context; the caller then frees the workspace. */
+void htree_destroy(htree_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HTREE_H */

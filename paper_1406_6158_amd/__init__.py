@@ -1,0 +1,169 @@
+"""MI355X (gfx950) library for the force path of the hybrid hard/soft tree
+method for collision-less N-body systems (Watanabe & Nakasato,
+arXiv:1406.6158): octree soft force, neighbour-search hard force and the
+two-timestep leapfrog, behind the C ABI of include/htree.h.
+
+``HTree`` is a thin torch-facing wrapper: torch allocates the device
+workspace and provides the stream; all computation happens in libhtree's HIP
+kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+from ._abi import (F_POT, F_TIMING, HTREE_EINVAL, HTREE_ENOMEM, HTREE_EOVERFLOW, HTREE_ESTATE,
+                   HTreeError, Params, Counters, check, default_params, lib, workspace_bytes)
+
+__all__ = ["HTree", "Params", "Counters", "HTreeError", "default_params", "workspace_bytes",
+           "lib", "F_POT", "F_TIMING", "HTREE_EINVAL", "HTREE_ENOMEM", "HTREE_EOVERFLOW",
+           "HTREE_ESTATE"]
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+class HTree:
+    """One particle system on one GPU.
+
+    ``params`` is a ``Params`` (see ``default_params``); ``n`` the particle
+    count.  The workspace is a torch uint8 tensor on ``device``; calls are
+    enqueued on ``stream`` (default: torch's current stream at construction).
+    """
+
+    def __init__(self, n: int, params: Params, device="cuda", stream=None):
+        import torch
+        self.torch = torch
+        self.n = int(n)
+        self.params = params
+        self.device = torch.device(device)
+        with torch.cuda.device(self.device):
+            self.stream = stream if stream is not None else torch.cuda.current_stream()
+            nbytes = workspace_bytes(params, self.n)
+            if nbytes == 0:
+                raise HTreeError(HTREE_EINVAL, lib().htree_last_error().decode())
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            h = C.c_void_p()
+            check(lib().htree_create(C.byref(h), C.byref(params), self.n,
+                                     C.c_void_p(self.workspace.data_ptr()), nbytes,
+                                     C.c_void_p(self.stream.cuda_stream)))
+        self._h = h
+
+    # -- lifetime ---------------------------------------------------------------
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            self.sync_stream()
+            lib().htree_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def sync_stream(self):
+        self.stream.synchronize()
+
+    # -- helpers ----------------------------------------------------------------
+    def _dev(self, t, dtype, shape):
+        torch = self.torch
+        t = torch.as_tensor(t)
+        t = t.to(device=self.device, dtype=dtype).contiguous()
+        if tuple(t.shape) != shape:
+            raise ValueError("expected shape %s, got %s" % (shape, tuple(t.shape)))
+        return t
+
+    def _new(self, dtype, shape):
+        return self.torch.empty(shape, dtype=dtype, device=self.device)
+
+    # -- ABI --------------------------------------------------------------------
+    def set_state(self, x, v, m):
+        torch = self.torch
+        n = self.n
+        self._x = self._dev(x, torch.float64, (3, n))
+        self._v = None if v is None else self._dev(v, torch.float32, (3, n))
+        self._m = self._dev(m, torch.float32, (n,))
+        check(lib().htree_set_state(self._h, _ptr(self._x), _ptr(self._v), _ptr(self._m)))
+        return self
+
+    def build_tree(self):
+        check(lib().htree_build_tree(self._h))
+        return self
+
+    def soft_force(self, out=None, pot=None, want_pot=False):
+        torch = self.torch
+        if out is None:
+            out = self._new(torch.float32, (3, self.n))
+        if want_pot and pot is None:
+            pot = self._new(torch.float32, (self.n,))
+        check(lib().htree_soft_force(self._h, _ptr(out), _ptr(pot)))
+        return (out, pot) if want_pot else out
+
+    def hard_force(self, out=None, ngb=None):
+        torch = self.torch
+        if out is None:
+            out = self._new(torch.float32, (3, self.n))
+        if ngb is None:
+            ngb = self._new(torch.int32, (self.n,))
+        check(lib().htree_hard_force(self._h, _ptr(out), _ptr(ngb)))
+        return out, ngb
+
+    def kick_drift(self, dt_kick, acc=None, dt_drift=0.0):
+        a = None if acc is None else self._dev(acc, self.torch.float32, (3, self.n))
+        check(lib().htree_kick_drift(self._h, float(dt_kick), _ptr(a), float(dt_drift)))
+        self._keep = a
+        return self
+
+    def step(self, n_soft_steps=1):
+        check(lib().htree_step(self._h, int(n_soft_steps)))
+        return self
+
+    def get_state(self):
+        torch = self.torch
+        x = self._new(torch.float64, (3, self.n))
+        v = self._new(torch.float32, (3, self.n))
+        check(lib().htree_get_state(self._h, _ptr(x), _ptr(v)))
+        return x, v
+
+    def sync(self):
+        check(lib().htree_sync(self._h))
+
+    def stats(self) -> dict:
+        c = Counters()
+        check(lib().htree_stats(self._h, C.byref(c)))
+        return c.as_dict()
+
+    def group_counts(self):
+        import numpy as np
+        ng = (self.n + self.params.group_size - 1) // self.params.group_size
+        a = [np.zeros(ng, np.int32) for _ in range(3)]
+        check(lib().htree_group_counts(self._h, *[C.c_void_p(v.ctypes.data) for v in a]))
+        return tuple(a)
+
+    def export_keys(self):
+        import numpy as np
+        keys = np.zeros(self.n, np.uint64)
+        perm = np.zeros(self.n, np.int32)
+        fr = np.zeros(4)
+        check(lib().htree_export_keys(self._h, C.c_void_p(keys.ctypes.data),
+                                      C.c_void_p(perm.ctypes.data), C.c_void_p(fr.ctypes.data)))
+        return keys, perm, fr[:3].copy(), float(fr[3])
+
+    def export_nodes(self):
+        import numpy as np
+        nn = int(lib().htree_node_count(self._h))
+        if nn < 0:
+            check(-3)
+        d = dict(level=np.zeros(nn, np.int32), first=np.zeros(nn, np.int32),
+                 count=np.zeros(nn, np.int32), M=np.zeros(nn), com=np.zeros((3, nn)))
+        check(lib().htree_export_nodes(self._h, *[C.c_void_p(d[k].ctypes.data) for k in
+                                                  ("level", "first", "count", "M", "com")]))
+        return d

@@ -1,0 +1,550 @@
+// api.hip -- host implementation of the C ABI declared in include/htree.h:
+// parameter validation, workspace carving, stream-ordered orchestration of
+// the build / force / integrator kernels, status and counters.
+#include "../../include/htree.h"
+#include "htree_dev.h"
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+
+using namespace htree;
+
+namespace {
+
+thread_local std::string g_err;
+
+htree_status fail(htree_status code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+htree_status fail(htree_status code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_OK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(HTREE_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));          \
+    } while (0)
+
+constexpr int64_t kMaxN = (int64_t)1 << 27;
+
+bool is_fin(double v) { return isfinite(v) != 0; }
+
+htree_status validate(const htree_params *p, int64_t n) {
+    if (!p) return fail(HTREE_EINVAL, "params is NULL");
+    if (n < 1 || n > kMaxN) return fail(HTREE_EINVAL, "n = %lld outside [1, 2^27]", (long long)n);
+    if (!is_fin(p->G) || p->G <= 0) return fail(HTREE_EINVAL, "G must be finite and > 0");
+    if (!is_fin(p->eps) || p->eps <= 0) return fail(HTREE_EINVAL, "eps must be finite and > 0");
+    if (!is_fin(p->theta) || p->theta < 0) return fail(HTREE_EINVAL, "theta must be >= 0");
+    if (p->hybrid != 0 && p->hybrid != 1) return fail(HTREE_EINVAL, "hybrid must be 0 or 1");
+    if (p->hybrid && !(is_fin(p->R1) && is_fin(p->R2) && p->R1 > 0 && p->R2 > p->R1))
+        return fail(HTREE_EINVAL, "hybrid mode needs 0 < R1 < R2");
+    if (!is_fin(p->dt_soft)) return fail(HTREE_EINVAL, "dt_soft must be finite");
+    if (p->n_sub < 1 || p->n_sub > 1024) return fail(HTREE_EINVAL, "n_sub must be in [1, 1024]");
+    if (p->n_crit < 1 || p->n_crit > 4096) return fail(HTREE_EINVAL, "n_crit must be in [1, 4096]");
+    if (p->group_size != 64) return fail(HTREE_EINVAL, "group_size must be 64");
+    if (p->precision != 0) return fail(HTREE_EINVAL, "precision must be 0 (FP32 interactions)");
+    if (p->flags & ~(HTREE_F_POT | HTREE_F_TIMING)) return fail(HTREE_EINVAL, "unknown flags");
+    return HTREE_OK;
+}
+
+// Upper bound on the node count: at each of the levels 0..20 the internal
+// nodes hold disjoint sets of >= n_crit particles, and leaves are disjoint and
+// non-empty.
+int64_t max_nodes(int64_t n, int n_crit) { return 1 + 21 * (n / n_crit) + n; }
+
+struct Carver {
+    char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(int64_t count) {
+        off = (off + 255) & ~(size_t)255;
+        T *p = base ? (T *)(base + off) : nullptr;
+        off += sizeof(T) * (size_t)(count > 0 ? count : 1);
+        return p;
+    }
+};
+
+}  // namespace
+
+struct htree_ctx {
+    htree_params p;
+    int64_t n = 0, ng = 0;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    BuildBufs B;
+    float *tmp3 = nullptr;             // [3][n] caller-order input staged in key order
+    float *pot = nullptr;              // [n] key order
+    int32_t *ngb = nullptr;            // [n] key order
+    uint32_t *gcount = nullptr;        // [3][ng]
+    unsigned long long *tally = nullptr;  // [4]
+    bool tree = false, moments = false, have_soft = false, have_hard = false;
+    bool forces_current = false;
+    hipEvent_t ev[8] = {};
+    bool timing = false;
+    float ms[4] = {0, 0, 0, 0};
+    bool ev_used[4] = {false, false, false, false};
+};
+
+namespace {
+
+void carve(Carver &C, htree_ctx *c) {
+    const int64_t n = c->n;
+    BuildBufs &B = c->B;
+    B.n = n;
+    B.n_crit = c->p.n_crit;
+    B.nnmax = max_nodes(n, c->p.n_crit);
+    const int64_t nnmax = B.nnmax;
+    for (int k = 0; k < 2; k++) {
+        B.x[k] = C.take<double>(3 * n);
+        B.v[k] = C.take<float>(3 * n);
+        B.m[k] = C.take<float>(n);
+        B.perm[k] = C.take<uint32_t>(n);
+        B.as[k] = C.take<float>(3 * n);
+        B.ah[k] = C.take<float>(3 * n);
+        B.key[k] = C.take<uint64_t>(n);
+        B.idx[k] = C.take<uint32_t>(n);
+    }
+    B.src = C.take<double4>(n);
+    int64_t hb = 256 * sort_blocks(nnmax);
+    B.hist = C.take<uint32_t>(hb + (int64_t)scan_partials(hb));
+    B.bbox_part = C.take<double>(6 * 1024);
+    B.frame = C.take<Frame>(1);
+    B.status = C.take<uint32_t>(4);
+    B.cpl = C.take<int8_t>(n);
+    B.leaflev = C.take<int8_t>(n);
+    B.nstart = C.take<uint32_t>(n + 1);
+    int64_t sp = (int64_t)scan_partials(n + 1);
+    int64_t sp2 = (int64_t)scan_partials(256 * sort_blocks(n));
+    B.scan_part = C.take<uint32_t>(sp > sp2 ? sp : sp2);
+    B.nn = C.take<uint32_t>(4);
+    B.pre_key = C.take<uint32_t>(nnmax);
+    B.pre_val = C.take<uint32_t>(nnmax);
+    B.lvl_key2 = C.take<uint32_t>(nnmax);
+    B.bfs2pre = C.take<uint32_t>(nnmax);
+    B.pre2bfs = C.take<uint32_t>(nnmax);
+    B.pre_first = C.take<uint32_t>(nnmax);
+    B.pre_count = C.take<uint32_t>(nnmax);
+    B.node = C.take<Node>(nnmax);
+    B.S = C.take<double>(3 * nnmax);
+    B.arrive = C.take<uint32_t>(nnmax);
+    c->tmp3 = C.take<float>(3 * n);
+    c->pot = C.take<float>(n);
+    c->ngb = C.take<int32_t>(n);
+    c->gcount = C.take<uint32_t>(3 * c->ng);
+    c->tally = C.take<unsigned long long>(4);
+}
+
+size_t footprint(const htree_params *p, int64_t n) {
+    htree_ctx tmp;
+    tmp.p = *p;
+    tmp.n = n;
+    tmp.ng = (n + p->group_size - 1) / p->group_size;
+    Carver C{nullptr};
+    carve(C, &tmp);
+    return (C.off + 255) & ~(size_t)255;
+}
+
+ForceArgs force_args(htree_ctx *c) {
+    ForceArgs A;
+    const BuildBufs &B = c->B;
+    A.node = B.node;
+    A.src = B.src;
+    A.x = B.x[B.cur];
+    A.frame = B.frame;
+    A.n = c->n;
+    A.g = c->p.group_size;
+    A.n_groups = c->ng;
+    A.G = (float)c->p.G;
+    A.eps2 = (float)(c->p.eps * c->p.eps);
+    A.R2f = (float)c->p.R2;
+    A.invdR = c->p.hybrid ? (float)(1.0 / (c->p.R2 - c->p.R1)) : 0.0f;
+    A.R2sq = c->p.R2 * c->p.R2;
+    A.acc = nullptr;
+    A.pot = nullptr;
+    A.ngb = nullptr;
+    A.gcount = c->gcount;
+    A.tally = c->tally;
+    A.status = B.status;
+    return A;
+}
+
+void ev_begin(htree_ctx *c, int k) {
+    if (c->timing) (void)hipEventRecord(c->ev[2 * k], c->stream);
+}
+void ev_end(htree_ctx *c, int k) {
+    if (c->timing) {
+        (void)hipEventRecord(c->ev[2 * k + 1], c->stream);
+        c->ev_used[k] = true;
+    }
+}
+
+htree_status do_build(htree_ctx *c, bool moments) {
+    ev_begin(c, 0);
+    launch_bbox_keys(c->B, c->stream);
+    launch_sort(c->B, c->stream);
+    launch_gather(c->B, c->stream);
+    launch_topology(c->B, moments, c->stream);
+    ev_end(c, 0);
+    HIP_OK(hipGetLastError());
+    c->tree = true;
+    c->moments = moments;
+    return HTREE_OK;
+}
+
+htree_status do_soft(htree_ctx *c) {
+    if (!c->tree || !c->moments) return fail(HTREE_ESTATE, "soft_force needs a current tree");
+    ForceArgs A = force_args(c);
+    A.acc = c->B.as[c->B.cur];
+    const bool pot = (c->p.flags & HTREE_F_POT) != 0;
+    A.pot = pot ? c->pot : nullptr;
+    ev_begin(c, 1);
+    launch_zero_u32((uint32_t *)c->tally, 2, c->stream);
+    launch_soft(A, c->p.hybrid != 0, pot, c->stream);
+    ev_end(c, 1);
+    HIP_OK(hipGetLastError());
+    c->have_soft = true;
+    return HTREE_OK;
+}
+
+htree_status do_hard(htree_ctx *c) {
+    if (!c->p.hybrid) return fail(HTREE_EINVAL, "hard_force needs hybrid mode");
+    if (!c->tree) return fail(HTREE_ESTATE, "hard_force needs a current tree");
+    ForceArgs A = force_args(c);
+    A.acc = c->B.ah[c->B.cur];
+    A.ngb = c->ngb;
+    ev_begin(c, 2);
+    launch_zero_u32((uint32_t *)(c->tally + 1), 4, c->stream);
+    launch_hard(A, c->stream);
+    ev_end(c, 2);
+    HIP_OK(hipGetLastError());
+    c->have_hard = true;
+    return HTREE_OK;
+}
+
+htree_status kick(htree_ctx *c, double ks, double kh, double dt_drift) {
+    BuildBufs &B = c->B;
+    const int k = B.cur;
+    launch_kick_drift(B.x[k], B.v[k], ks != 0.0 ? B.as[k] : nullptr, (float)ks,
+                      kh != 0.0 ? B.ah[k] : nullptr, (float)kh, dt_drift, c->n, c->stream);
+    HIP_OK(hipGetLastError());
+    if (dt_drift != 0.0) c->tree = c->moments = c->forces_current = false;
+    return HTREE_OK;
+}
+
+htree_status ensure_forces(htree_ctx *c) {
+    if (c->forces_current) return HTREE_OK;
+    htree_status st = do_build(c, true);
+    if (st) return st;
+    if ((st = do_soft(c))) return st;
+    if (c->p.hybrid && (st = do_hard(c))) return st;
+    c->forces_current = true;
+    return HTREE_OK;
+}
+
+#define CTX_CHECK(c)                                                         \
+    do {                                                                     \
+        if (!(c)) return fail(HTREE_EINVAL, "context is NULL");             \
+        HIP_OK(hipSetDevice((c)->device));                                   \
+    } while (0)
+
+}  // namespace
+
+extern "C" {
+
+void htree_default_params(htree_params *p) {
+    if (!p) return;
+    p->G = 1.0;
+    p->eps = 0.01;
+    p->theta = 0.5;
+    p->R1 = 0.05;
+    p->R2 = 0.1;
+    p->dt_soft = 1.0 / 16.0;
+    p->n_sub = 4;
+    p->hybrid = 1;
+    p->n_crit = 16;
+    p->group_size = 64;
+    p->precision = 0;
+    p->flags = 0;
+}
+
+size_t htree_workspace_bytes(const htree_params *p, int64_t n) {
+    if (validate(p, n) != HTREE_OK) return 0;
+    return footprint(p, n);
+}
+
+htree_status htree_create(htree_ctx **out, const htree_params *p, int64_t n, void *ws,
+                          size_t ws_bytes, void *stream) {
+    if (!out) return fail(HTREE_EINVAL, "out is NULL");
+    *out = nullptr;
+    htree_status st = validate(p, n);
+    if (st) return st;
+    size_t need = footprint(p, n);
+    if (!ws) return fail(HTREE_EINVAL, "workspace is NULL");
+    if (((uintptr_t)ws & 255u) != 0) return fail(HTREE_EINVAL, "workspace not 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(HTREE_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, need);
+    htree_ctx *c = new htree_ctx();
+    c->p = *p;
+    c->n = n;
+    c->ng = (n + p->group_size - 1) / p->group_size;
+    c->stream = (hipStream_t)stream;
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(HTREE_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    }
+    Carver C{(char *)ws};
+    carve(C, c);
+    c->B.invth2 = 1.0 / (p->theta * p->theta);
+    c->B.R2 = p->hybrid ? p->R2 : 0.0;
+    c->B.cur = 0;
+    c->timing = (p->flags & HTREE_F_TIMING) != 0;
+    if (c->timing)
+        for (int k = 0; k < 8; k++) (void)hipEventCreate(&c->ev[k]);
+    launch_zero_u32(c->B.status, 4, c->stream);
+    launch_zero_u32(c->B.nn, 4, c->stream);
+    e = hipGetLastError();
+    if (e != hipSuccess) {
+        delete c;
+        return fail(HTREE_EDEVICE, "launch: %s", hipGetErrorString(e));
+    }
+    *out = c;
+    return HTREE_OK;
+}
+
+htree_status htree_set_state(htree_ctx *c, const double *d_x, const float *d_v, const float *d_m) {
+    CTX_CHECK(c);
+    if (!d_x || !d_m) return fail(HTREE_EINVAL, "x and m are required");
+    BuildBufs &B = c->B;
+    B.cur = 0;
+    launch_set_state(d_x, d_v, d_m, B.x[0], B.v[0], B.m[0], B.perm[0], c->n, c->stream);
+    launch_zero_u32((uint32_t *)B.as[0], 3 * c->n, c->stream);
+    launch_zero_u32((uint32_t *)B.ah[0], 3 * c->n, c->stream);
+    HIP_OK(hipGetLastError());
+    c->tree = c->moments = c->have_soft = c->have_hard = c->forces_current = false;
+    return HTREE_OK;
+}
+
+htree_status htree_build_tree(htree_ctx *c) {
+    CTX_CHECK(c);
+    c->forces_current = false;
+    return do_build(c, true);
+}
+
+htree_status htree_soft_force(htree_ctx *c, float *d_acc, float *d_pot) {
+    CTX_CHECK(c);
+    htree_status st = do_soft(c);
+    if (st) return st;
+    const BuildBufs &B = c->B;
+    if (d_acc) launch_scatter3(B.as[B.cur], B.perm[B.cur], d_acc, c->n, c->stream);
+    if (d_pot) {
+        if (!(c->p.flags & HTREE_F_POT))
+            return fail(HTREE_EINVAL, "d_pot given but the context lacks HTREE_F_POT");
+        launch_scatter1f(c->pot, B.perm[B.cur], d_pot, c->n, c->stream);
+    }
+    HIP_OK(hipGetLastError());
+    return HTREE_OK;
+}
+
+htree_status htree_hard_force(htree_ctx *c, float *d_acc, int32_t *d_ngb) {
+    CTX_CHECK(c);
+    htree_status st = do_hard(c);
+    if (st) return st;
+    const BuildBufs &B = c->B;
+    if (d_acc) launch_scatter3(B.ah[B.cur], B.perm[B.cur], d_acc, c->n, c->stream);
+    if (d_ngb) launch_scatter1i(c->ngb, B.perm[B.cur], d_ngb, c->n, c->stream);
+    HIP_OK(hipGetLastError());
+    return HTREE_OK;
+}
+
+htree_status htree_kick_drift(htree_ctx *c, double dt_kick, const float *d_acc, double dt_drift) {
+    CTX_CHECK(c);
+    if (!is_fin(dt_kick) || !is_fin(dt_drift)) return fail(HTREE_EINVAL, "non-finite dt");
+    BuildBufs &B = c->B;
+    const int k = B.cur;
+    if (d_acc) {
+        launch_gather3(d_acc, B.perm[k], c->tmp3, c->n, c->stream);
+        launch_kick_drift(B.x[k], B.v[k], c->tmp3, (float)dt_kick, nullptr, 0.f, dt_drift, c->n,
+                          c->stream);
+    } else {
+        if (!c->have_soft && !c->have_hard)
+            return fail(HTREE_ESTATE, "no kept accelerations to kick with");
+        launch_kick_drift(B.x[k], B.v[k], c->have_soft ? B.as[k] : nullptr, (float)dt_kick,
+                          c->have_hard ? B.ah[k] : nullptr, (float)dt_kick, dt_drift, c->n,
+                          c->stream);
+    }
+    HIP_OK(hipGetLastError());
+    if (dt_drift != 0.0) c->tree = c->moments = c->forces_current = false;
+    return HTREE_OK;
+}
+
+htree_status htree_step(htree_ctx *c, int32_t n_soft) {
+    CTX_CHECK(c);
+    if (n_soft < 0) return fail(HTREE_EINVAL, "n_soft_steps must be >= 0");
+    htree_status st = ensure_forces(c);
+    if (st) return st;
+    const double dts = c->p.dt_soft;
+    for (int32_t s = 0; s < n_soft; s++) {
+        if (!c->p.hybrid) {
+            if ((st = kick(c, 0.5 * dts, 0.0, dts))) return st;
+            if ((st = do_build(c, true))) return st;
+            if ((st = do_soft(c))) return st;
+            if ((st = kick(c, 0.5 * dts, 0.0, 0.0))) return st;
+            c->forces_current = true;
+            continue;
+        }
+        const int nsub = c->p.n_sub;
+        const double dth = dts / nsub;
+        for (int h = 0; h < nsub; h++) {
+            // opening kicks (soft half-kick on the first substep) and the drift
+            if ((st = kick(c, h == 0 ? 0.5 * dts : 0.0, 0.5 * dth, dth))) return st;
+            const bool last = h == nsub - 1;
+            if ((st = do_build(c, last))) return st;
+            if (last && (st = do_soft(c))) return st;
+            if ((st = do_hard(c))) return st;
+            if ((st = kick(c, last ? 0.5 * dts : 0.0, 0.5 * dth, 0.0))) return st;
+        }
+        c->forces_current = true;
+    }
+    return HTREE_OK;
+}
+
+htree_status htree_get_state(htree_ctx *c, double *d_x, float *d_v) {
+    CTX_CHECK(c);
+    const BuildBufs &B = c->B;
+    if (d_x) launch_scatter_x(B.x[B.cur], B.perm[B.cur], d_x, c->n, c->stream);
+    if (d_v) launch_scatter3(B.v[B.cur], B.perm[B.cur], d_v, c->n, c->stream);
+    HIP_OK(hipGetLastError());
+    return HTREE_OK;
+}
+
+htree_status htree_sync(htree_ctx *c) {
+    CTX_CHECK(c);
+    HIP_OK(hipStreamSynchronize(c->stream));
+    uint32_t st = 0;
+    HIP_OK(hipMemcpy(&st, c->B.status, sizeof st, hipMemcpyDeviceToHost));
+    if (st & kStatusNonFinite) return fail(HTREE_EINVAL, "non-finite particle position");
+    if (st & kStatusOverflow) return fail(HTREE_EOVERFLOW, "device capacity exceeded");
+    return HTREE_OK;
+}
+
+htree_status htree_stats(htree_ctx *c, htree_counters *out) {
+    CTX_CHECK(c);
+    if (!out) return fail(HTREE_EINVAL, "out is NULL");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    unsigned long long t[4];
+    uint32_t nn = 0;
+    HIP_OK(hipMemcpy(t, c->tally, sizeof t, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(&nn, c->B.nn, sizeof nn, hipMemcpyDeviceToHost));
+    memset(out, 0, sizeof *out);
+    out->n = c->n;
+    out->n_groups = c->ng;
+    out->n_nodes = nn;
+    out->soft_interactions = (int64_t)t[0];
+    out->hard_candidates = (int64_t)t[1];
+    out->hard_pairs = (int64_t)t[2];
+    if (c->have_soft) {
+        int64_t ng = c->ng;
+        uint32_t *h = new uint32_t[3 * ng];
+        hipError_t e = hipMemcpy(h, c->gcount, sizeof(uint32_t) * 3 * ng, hipMemcpyDeviceToHost);
+        if (e == hipSuccess)
+            for (int64_t k = 0; k < ng; k++) {
+                out->soft_cells += h[k];
+                out->soft_far += h[ng + k];
+                out->soft_near += h[2 * ng + k];
+            }
+        delete[] h;
+        HIP_OK(e);
+    }
+    if (c->timing) {
+        float *dst[3] = {&out->ms_build, &out->ms_soft, &out->ms_hard};
+        for (int k = 0; k < 3; k++)
+            if (c->ev_used[k]) HIP_OK(hipEventElapsedTime(dst[k], c->ev[2 * k], c->ev[2 * k + 1]));
+    }
+    return HTREE_OK;
+}
+
+htree_status htree_group_counts(htree_ctx *c, int32_t *n_cells, int32_t *n_far, int32_t *n_near) {
+    CTX_CHECK(c);
+    if (!c->have_soft) return fail(HTREE_ESTATE, "no soft_force has run");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    int32_t *dst[3] = {n_cells, n_far, n_near};
+    for (int k = 0; k < 3; k++)
+        if (dst[k])
+            HIP_OK(hipMemcpy(dst[k], c->gcount + k * c->ng, sizeof(int32_t) * c->ng,
+                             hipMemcpyDeviceToHost));
+    return HTREE_OK;
+}
+
+htree_status htree_export_keys(htree_ctx *c, uint64_t *keys, int32_t *perm, double *frame4) {
+    CTX_CHECK(c);
+    if (!c->tree) return fail(HTREE_ESTATE, "no current tree");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    const BuildBufs &B = c->B;
+    if (keys) HIP_OK(hipMemcpy(keys, B.key[0], sizeof(uint64_t) * c->n, hipMemcpyDeviceToHost));
+    if (perm)
+        HIP_OK(hipMemcpy(perm, B.perm[B.cur], sizeof(int32_t) * c->n, hipMemcpyDeviceToHost));
+    if (frame4) {
+        Frame F;
+        HIP_OK(hipMemcpy(&F, B.frame, sizeof F, hipMemcpyDeviceToHost));
+        frame4[0] = F.lo[0];
+        frame4[1] = F.lo[1];
+        frame4[2] = F.lo[2];
+        frame4[3] = F.side;
+    }
+    return HTREE_OK;
+}
+
+int64_t htree_node_count(htree_ctx *c) {
+    if (!c) return -1;
+    if (hipSetDevice(c->device) != hipSuccess) return -1;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return -1;
+    uint32_t nn = 0;
+    if (hipMemcpy(&nn, c->B.nn, sizeof nn, hipMemcpyDeviceToHost) != hipSuccess) return -1;
+    return nn;
+}
+
+htree_status htree_export_nodes(htree_ctx *c, int32_t *level, int32_t *first, int32_t *count,
+                                double *mass, double *com) {
+    CTX_CHECK(c);
+    if (!c->tree) return fail(HTREE_ESTATE, "no current tree");
+    int64_t nn = htree_node_count(c);
+    if (nn < 0) return fail(HTREE_EDEVICE, "cannot read the node count");
+    Node *h = new Node[nn > 0 ? nn : 1];
+    hipError_t e = hipMemcpy(h, c->B.node, sizeof(Node) * nn, hipMemcpyDeviceToHost);
+    if (e == hipSuccess)
+        for (int64_t k = 0; k < nn; k++) {
+            if (level) level[k] = (int32_t)(h[k].meta >> 8);
+            if (first) first[k] = (int32_t)h[k].first;
+            if (count) count[k] = (int32_t)h[k].count;
+            if (mass) mass[k] = h[k].M;
+            if (com)
+                for (int a = 0; a < 3; a++) com[a * nn + k] = h[k].com[a];
+        }
+    delete[] h;
+    HIP_OK(e);
+    return HTREE_OK;
+}
+
+const char *htree_last_error(void) { return g_err.c_str(); }
+
+void htree_destroy(htree_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    if (c->timing)
+        for (int k = 0; k < 8; k++)
+            if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+    delete c;
+}
+
+}  // extern "C"

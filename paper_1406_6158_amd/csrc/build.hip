@@ -1,0 +1,556 @@
+// build.hip -- octree construction on the GPU (section III.A.1 of the paper,
+// redesigned for gfx950): bounding box, 63-bit Morton keys, stable LSD radix
+// sort, state permutation, topology from the sorted keys, bottom-up moments.
+//
+// Topology without recursion.  The paper splits the sorted array recursively
+// by 3-bit key digits while a cell holds >= n_crit particles.  The same tree
+// is obtained in parallel: with c_i the number of leading 3-bit digits that
+// key i shares with key i-1, and D_i the largest number of digits shared by
+// the two ends of any window of n_crit consecutive keys containing i, the cell
+// of level l around particle i holds >= n_crit particles iff l <= D_i.  Hence
+// particle i's leaf is at level L_i = min(D_i + 1, 21) (0 if n < n_crit), and
+// the nodes that begin at sorted position i are the cells of levels
+// c_i + 1 .. L_i.  Enumerating them by position gives the depth-first
+// (pre-order) node sequence; a stable partition by level gives level order, in
+// which the children of a node are contiguous.
+#include "htree_dev.h"
+
+#include <math.h>
+
+namespace htree {
+
+// ---------------------------------------------------------------------------
+// small wave / block helpers
+// ---------------------------------------------------------------------------
+// Exclusive scan across a block of NT threads; returns the prefix and writes
+// the block total.
+template <int NT>
+__device__ inline uint32_t block_excl_scan(uint32_t v, uint32_t *sh, uint32_t &total) {
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    uint32_t inc = wave_incl_scan(v);
+    if (lane == 63) sh[w] = inc;
+    __syncthreads();
+    if (w == 0) {
+        uint32_t t = lane < NT / 64 ? sh[lane] : 0u;
+        uint32_t ti = wave_incl_scan(t);
+        if (lane < NT / 64) sh[lane] = ti - t;
+        if (lane == NT / 64 - 1) sh[NT / 64] = ti;
+    }
+    __syncthreads();
+    uint32_t r = inc - v + sh[w];
+    total = sh[NT / 64];
+    __syncthreads();
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of a u32 array (in place), with the grand total
+// ---------------------------------------------------------------------------
+constexpr int kScanNT = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanChunk = kScanNT * kScanItems;
+
+size_t scan_partials(int64_t n) { return (size_t)((n + kScanChunk - 1) / kScanChunk) + 1; }
+
+__global__ __launch_bounds__(kScanNT) void k_scan_reduce(const uint32_t *data, int64_t n,
+                                                         uint32_t *part) {
+    __shared__ uint32_t sh[kScanNT / 64 + 1];
+    int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    uint32_t s = 0;
+    for (int k = 0; k < kScanItems; k++) {
+        int64_t i = base + k * kScanNT + threadIdx.x;
+        if (i < n) s += data[i];
+    }
+    uint32_t tot;
+    block_excl_scan<kScanNT>(s, sh, tot);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_partials(uint32_t *part, int64_t np,
+                                                        uint32_t *total) {
+    __shared__ uint32_t sh[1024 / 64 + 1];
+    uint32_t carry = 0;
+    for (int64_t c = 0; c < np; c += 1024) {
+        int64_t i = c + threadIdx.x;
+        uint32_t v = i < np ? part[i] : 0u;
+        uint32_t tot;
+        uint32_t ex = block_excl_scan<1024>(v, sh, tot);
+        if (i < np) part[i] = ex + carry;
+        carry += tot;
+    }
+    if (threadIdx.x == 0 && total) *total = carry;
+}
+
+__global__ __launch_bounds__(kScanNT) void k_scan_down(uint32_t *data, int64_t n,
+                                                       const uint32_t *part) {
+    __shared__ uint32_t sh[kScanNT / 64 + 1];
+    int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    // each thread owns kScanItems consecutive elements
+    uint32_t v[kScanItems];
+    uint32_t s = 0;
+    int64_t t0 = base + (int64_t)threadIdx.x * kScanItems;
+    for (int k = 0; k < kScanItems; k++) {
+        int64_t i = t0 + k;
+        v[k] = i < n ? data[i] : 0u;
+        s += v[k];
+    }
+    uint32_t tot;
+    uint32_t ex = block_excl_scan<kScanNT>(s, sh, tot) + part[blockIdx.x];
+    for (int k = 0; k < kScanItems; k++) {
+        int64_t i = t0 + k;
+        if (i < n) data[i] = ex;
+        ex += v[k];
+    }
+}
+
+void launch_scan_u32(uint32_t *data, int64_t n, uint32_t *part, uint32_t *total, hipStream_t s) {
+    int64_t nb = (n + kScanChunk - 1) / kScanChunk;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanNT), 0, s, data, n, part);
+    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, nb, total);
+    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanNT), 0, s, data, n, part);
+}
+
+// ---------------------------------------------------------------------------
+// bounding box, frame and keys
+// ---------------------------------------------------------------------------
+constexpr int kBoxNT = 256;
+constexpr int kBoxBlocks = 1024;
+
+__global__ __launch_bounds__(kBoxNT) void k_bbox(const double *x, int64_t n, double *part,
+                                                 uint32_t *status) {
+    __shared__ double sh[kBoxNT / 64][6];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    bool bad = false;
+    for (int64_t i = (int64_t)blockIdx.x * kBoxNT + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kBoxNT) {
+        for (int a = 0; a < 3; a++) {
+            double v = x[a * n + i];
+            bad |= !isfinite(v);
+            lo[a] = fmin(lo[a], v);
+            hi[a] = fmax(hi[a], v);
+        }
+    }
+    if (bad) atomicOr(status, kStatusNonFinite);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int a = 0; a < 3; a++) {
+        lo[a] = wave_min(lo[a]);
+        hi[a] = wave_max(hi[a]);
+    }
+    if (lane == 0)
+        for (int a = 0; a < 3; a++) { sh[w][a] = lo[a]; sh[w][3 + a] = hi[a]; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 1; k < kBoxNT / 64; k++)
+            for (int a = 0; a < 3; a++) {
+                sh[0][a] = fmin(sh[0][a], sh[k][a]);
+                sh[0][3 + a] = fmax(sh[0][3 + a], sh[k][3 + a]);
+            }
+        for (int a = 0; a < 6; a++) part[blockIdx.x * 6 + a] = sh[0][a];
+    }
+}
+
+__global__ void k_frame(const double *part, int nb, Frame *F, double R2) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int b = 0; b < nb; b++)
+        for (int a = 0; a < 3; a++) {
+            lo[a] = fmin(lo[a], part[b * 6 + a]);
+            hi[a] = fmax(hi[a], part[b * 6 + 3 + a]);
+        }
+    // extent of the build frame u = x - lo: rounding is monotone, so the
+    // largest rounded difference is the rounded difference of the extremes
+    double ext = 0.0;
+    for (int a = 0; a < 3; a++) {
+        double e = hi[a] - lo[a];
+        if (e > ext) ext = e;
+    }
+    double side;
+    if (!(ext > 0.0)) {
+        side = 1.0;
+    } else {
+        int e;
+        double f = frexp(ext, &e);
+        side = (f == 0.5) ? ldexp(1.0, e - 1) : ldexp(1.0, e);
+    }
+    for (int a = 0; a < 3; a++) F->lo[a] = lo[a];
+    F->side = side;
+    F->scale = ldexp(1.0, kMaxLevel) / side;
+    // slack covers the rounding of build-frame differences against FP64 x
+    double R2p = R2 + ldexp(side, -40);
+    F->R2pad2 = R2p * R2p;
+}
+
+__device__ inline uint64_t spread3(uint32_t v) {
+    uint64_t x = v & 0x1fffffu;
+    x = (x | x << 32) & 0x1f00000000ffffull;
+    x = (x | x << 16) & 0x1f0000ff0000ffull;
+    x = (x | x << 8) & 0x100f00f00f00f00full;
+    x = (x | x << 4) & 0x10c30c30c30c30c3ull;
+    x = (x | x << 2) & 0x1249249249249249ull;
+    return x;
+}
+
+__device__ inline uint32_t compact3(uint64_t x) {
+    x &= 0x1249249249249249ull;
+    x = (x ^ (x >> 2)) & 0x10c30c30c30c30c3ull;
+    x = (x ^ (x >> 4)) & 0x100f00f00f00f00full;
+    x = (x ^ (x >> 8)) & 0x1f0000ff0000ffull;
+    x = (x ^ (x >> 16)) & 0x1f00000000ffffull;
+    x = (x ^ (x >> 32)) & 0x1fffffull;
+    return (uint32_t)x;
+}
+
+__global__ __launch_bounds__(256) void k_keys(const double *x, int64_t n, const Frame *F,
+                                              uint64_t *key, uint32_t *idx) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const double scale = F->scale;
+    const uint32_t qmax = (1u << kMaxLevel) - 1u;
+    uint32_t q[3];
+    for (int a = 0; a < 3; a++) {
+        double u = x[a * n + i] - F->lo[a];
+        double s = floor(u * scale);
+        q[a] = (s >= (double)qmax) ? qmax : (uint32_t)s;
+    }
+    key[i] = (spread3(q[0]) << 2) | (spread3(q[1]) << 1) | spread3(q[2]);
+    idx[i] = (uint32_t)i;
+}
+
+void launch_bbox_keys(const BuildBufs &B, hipStream_t s) {
+    int64_t n = B.n;
+    int nb = (int)((n + kBoxNT - 1) / kBoxNT);
+    if (nb > kBoxBlocks) nb = kBoxBlocks;
+    if (nb < 1) nb = 1;
+    const double *x = B.x[B.cur];
+    hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(kBoxNT), 0, s, x, n, B.bbox_part, B.status);
+    hipLaunchKernelGGL(k_frame, dim3(1), dim3(64), 0, s, B.bbox_part, nb, B.frame, B.R2);
+    hipLaunchKernelGGL(k_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n,
+                       B.frame, B.key[0], B.idx[0]);
+}
+
+// ---------------------------------------------------------------------------
+// stable LSD radix sort, 8-bit digits
+// ---------------------------------------------------------------------------
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_radix_hist(const K *key, int64_t nmax,
+                                                             const uint32_t *count_dev, int shift,
+                                                             uint32_t *hist, int64_t nb) {
+    __shared__ uint32_t cnt[256];
+    const int tid = threadIdx.x;
+    const int64_t n = count_dev ? (int64_t)*count_dev : nmax;
+    cnt[tid] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kSortTile;
+    for (int r = 0; r < kSortItems; r++) {
+        int64_t i = base + r * kSortThreads + tid;
+        if (i < n) atomicAdd(&cnt[(uint32_t)(key[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)tid * nb + blockIdx.x] = cnt[tid];
+}
+
+template <typename K>
+__global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
+    const K *key, const uint32_t *val, int64_t nmax, const uint32_t *count_dev, int shift,
+    const uint32_t *hist, int64_t nb, K *key_out, uint32_t *val_out) {
+    __shared__ uint32_t run[256];
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wcnt[kSortThreads / 64][256];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t n = count_dev ? (int64_t)*count_dev : nmax;
+    const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
+    if (tile0 >= n) return;
+    run[tid] = 0;
+    base[tid] = hist[(int64_t)tid * nb + blockIdx.x];
+    const uint64_t lt = lanemask_lt();
+    for (int r = 0; r < kSortItems; r++) {
+        int64_t i = tile0 + r * kSortThreads + tid;
+        bool valid = i < n;
+        K k = valid ? key[i] : (K)0;
+        uint32_t v = valid ? val[i] : 0u;
+        uint32_t d = (uint32_t)(k >> shift) & 255u;
+        uint64_t peers = __ballot(valid);
+        for (int b = 0; b < 8; b++) {
+            uint64_t m = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? m : ~m;
+        }
+        uint32_t rank = __popcll(peers & lt);
+        for (int j = 0; j < kSortThreads / 64; j++) wcnt[j][tid] = 0;
+        __syncthreads();
+        if (valid && rank == 0) wcnt[w][d] = __popcll(peers);
+        __syncthreads();
+        if (valid) {
+            uint32_t pre = 0;
+            for (int j = 0; j < w; j++) pre += wcnt[j][d];
+            uint32_t pos = base[d] + run[d] + pre + rank;
+            key_out[pos] = k;
+            val_out[pos] = v;
+        }
+        __syncthreads();
+        uint32_t add = 0;
+        for (int j = 0; j < kSortThreads / 64; j++) add += wcnt[j][tid];
+        run[tid] += add;
+        __syncthreads();
+    }
+    (void)lane;
+}
+
+template <typename K>
+static void radix_pass(const K *kin, const uint32_t *vin, K *kout, uint32_t *vout,
+                       uint32_t *hist, uint32_t *part, const uint32_t *count_dev, int64_t nmax,
+                       int shift, hipStream_t s) {
+    int64_t nb = sort_blocks(nmax);
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_radix_hist<K>, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kin, nmax,
+                       count_dev, shift, hist, nb);
+    launch_scan_u32(hist, 256 * nb, part, nullptr, s);
+    hipLaunchKernelGGL(k_radix_scatter<K>, dim3((unsigned)nb), dim3(kSortThreads), 0, s, kin, vin,
+                       nmax, count_dev, shift, hist, nb, kout, vout);
+}
+
+void launch_sort(BuildBufs &B, hipStream_t s) {
+    // keys are 63-bit: eight passes, the result lands back in buffer 0
+    for (int pass = 0; pass < 8; pass++) {
+        int a = pass & 1, b = a ^ 1;
+        radix_pass<uint64_t>(B.key[a], B.idx[a], B.key[b], B.idx[b], B.hist, B.scan_part, nullptr,
+                             B.n, 8 * pass, s);
+    }
+}
+
+void launch_radix_u32(uint32_t *key_in, uint32_t *val_in, uint32_t *key_out, uint32_t *val_out,
+                      uint32_t *hist, const uint32_t *count_dev, int64_t nmax, int shift,
+                      hipStream_t s) {
+    // partials for the histogram scan live just past the histogram itself
+    int64_t nb = sort_blocks(nmax);
+    if (nb < 1) nb = 1;
+    radix_pass<uint32_t>(key_in, val_in, key_out, val_out, hist, hist + 256 * nb, count_dev, nmax,
+                         shift, s);
+}
+
+// ---------------------------------------------------------------------------
+// permutation of the particle state into key order
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gather(
+    const uint32_t *idx, int64_t n, const Frame *F, const double *x0, const float *v0,
+    const float *m0, const uint32_t *p0, const float *as0, const float *ah0, double *x1, float *v1,
+    float *m1, uint32_t *p1, float *as1, float *ah1, double4 *src) {
+    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    uint32_t o = idx[p];
+    double xx[3];
+    for (int a = 0; a < 3; a++) {
+        xx[a] = x0[a * n + o];
+        x1[a * n + p] = xx[a];
+        v1[a * n + p] = v0[a * n + o];
+        as1[a * n + p] = as0[a * n + o];
+        ah1[a * n + p] = ah0[a * n + o];
+    }
+    float mm = m0[o];
+    m1[p] = mm;
+    p1[p] = p0[o];
+    src[p] = make_double4(xx[0] - F->lo[0], xx[1] - F->lo[1], xx[2] - F->lo[2], (double)mm);
+}
+
+void launch_gather(BuildBufs &B, hipStream_t s) {
+    int c = B.cur, d = c ^ 1;
+    int64_t n = B.n;
+    hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, B.idx[0], n,
+                       B.frame, B.x[c], B.v[c], B.m[c], B.perm[c], B.as[c], B.ah[c], B.x[d],
+                       B.v[d], B.m[d], B.perm[d], B.as[d], B.ah[d], B.src);
+    B.cur = d;
+}
+
+// ---------------------------------------------------------------------------
+// topology
+// ---------------------------------------------------------------------------
+// number of leading 3-bit digits two 63-bit keys share (21 if equal)
+__device__ inline int common_levels(uint64_t a, uint64_t b) {
+    uint64_t d = a ^ b;
+    if (d == 0) return kMaxLevel;
+    return (__clzll((long long)d) - 1) / 3;
+}
+
+__global__ __launch_bounds__(256) void k_cpl(const uint64_t *key, int64_t n, int n_crit,
+                                             int8_t *cpl, int8_t *dwin) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    uint64_t k = key[i];
+    cpl[i] = (int8_t)(i == 0 ? -1 : common_levels(key[i - 1], k));
+    // window starting at i
+    int64_t j = i + n_crit - 1;
+    dwin[i] = (int8_t)(j < n ? common_levels(k, key[j]) : -1);
+}
+
+__global__ __launch_bounds__(256) void k_leaflev(const int8_t *cpl, const int8_t *dwin, int64_t n,
+                                                 int n_crit, int8_t *leaflev, uint32_t *nstart) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    int D = -1;
+    int64_t s0 = i - n_crit + 1;
+    if (s0 < 0) s0 = 0;
+    for (int64_t s = s0; s <= i; s++) {
+        int d = dwin[s];   // -1 where the window runs past the end
+        if (d > D) D = d;
+    }
+    int L = D < 0 ? 0 : (D + 1 < kMaxLevel ? D + 1 : kMaxLevel);
+    leaflev[i] = (int8_t)L;
+    int c = cpl[i];
+    nstart[i] = (uint32_t)(L > c ? L - c : 0);
+    if (i == n - 1) nstart[n] = 0u;   // the scan's total must not see stale data
+}
+
+// end of the level-lev cell that starts at sorted position i
+__device__ inline uint32_t cell_end(const uint64_t *key, int64_t n, int64_t i, int lev) {
+    int sh = 3 * (kMaxLevel - lev);
+    uint64_t P = key[i] >> sh;
+    // gallop then bisect for the first j > i with a different prefix
+    int64_t lo = i, step = 1, hi;
+    for (;;) {
+        hi = lo + step;
+        if (hi >= n) { hi = n; break; }
+        if ((key[hi] >> sh) != P) break;
+        lo = hi;
+        step <<= 1;
+    }
+    // key[lo] has prefix P; key[hi] differs (or hi == n)
+    while (hi - lo > 1) {
+        int64_t mid = lo + ((hi - lo) >> 1);
+        if ((key[mid] >> sh) == P) lo = mid; else hi = mid;
+    }
+    return (uint32_t)hi;
+}
+
+__global__ __launch_bounds__(256) void k_emit_pre(const uint64_t *key, const int8_t *cpl,
+                                                  const uint32_t *nstart, int64_t n,
+                                                  uint32_t *pre_key, uint32_t *pre_val,
+                                                  uint32_t *pre_first, uint32_t *pre_count) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    uint32_t p0 = nstart[i], p1 = nstart[i + 1];
+    int lev = cpl[i] + 1;
+    for (uint32_t p = p0; p < p1; p++, lev++) {
+        pre_key[p] = (uint32_t)lev;
+        pre_val[p] = p;
+        pre_first[p] = (uint32_t)i;
+        pre_count[p] = cell_end(key, n, i, lev) - (uint32_t)i;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pre2bfs(const uint32_t *bfs2pre, const uint32_t *nn,
+                                                 uint32_t *pre2bfs) {
+    uint32_t b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= *nn) return;
+    pre2bfs[bfs2pre[b]] = b;
+}
+
+__global__ __launch_bounds__(256) void k_fill_nodes(
+    const uint64_t *key, const int8_t *leaflev, const uint32_t *nstart, const uint32_t *bfs2pre,
+    const uint32_t *pre2bfs, const uint32_t *lvl, const uint32_t *pre_first,
+    const uint32_t *pre_count, const uint32_t *nn, const Frame *F, double invth2, Node *node,
+    uint32_t *arrive) {
+    uint32_t b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= *nn) return;
+    uint32_t p = bfs2pre[b];
+    int lev = (int)lvl[b];
+    uint32_t first = pre_first[p], count = pre_count[p];
+    bool internal = lev < leaflev[first];
+    uint32_t child = 0, nch = 0;
+    if (internal) {
+        child = pre2bfs[p + 1];
+        uint32_t c = p + 1, end = first + count;
+        for (;;) {
+            nch++;
+            uint32_t e = pre_first[c] + pre_count[c];
+            if (e >= end) break;
+            c = nstart[e];
+        }
+        for (uint32_t k = 0; k < nch; k++) node[child + k].parent = b;
+    }
+    if (b == 0) node[0].parent = 0;
+    double l = ldexp(F->side, -lev);
+    uint64_t k0 = key[first];
+    Node &N = node[b];
+    N.first = first;
+    N.count = count;
+    N.child = child;
+    N.meta = nch | ((uint32_t)lev << 8);
+    N.l = l;
+    N.rb2 = (l * l) * invth2;
+    for (int a = 0; a < 3; a++) {
+        uint32_t q = compact3(k0 >> (2 - a));
+        N.blo[a] = (double)(q >> (kMaxLevel - lev)) * l;
+    }
+    arrive[b] = 0;
+}
+
+// Bottom-up moments: each leaf sums its particles in sorted order, then the
+// last child to arrive at a parent sums the children in octant order.
+__global__ __launch_bounds__(256) void k_moments(Node *node, const double4 *src, double *S,
+                                                 const uint32_t *nn_dev, int64_t nnmax,
+                                                 uint32_t *arrive) {
+    uint32_t b = blockIdx.x * 256 + threadIdx.x;
+    uint32_t nn = *nn_dev;
+    if (b >= nn) return;
+    uint32_t meta = node[b].meta;
+    if ((meta & 255u) != 0) return;   // internal: done by the last child
+    double M = 0.0, s[3] = {0.0, 0.0, 0.0};
+    uint32_t f = node[b].first, c = node[b].count;
+    for (uint32_t i = f; i < f + c; i++) {
+        double4 q = src[i];
+        M += q.w;
+        s[0] = fma(q.w, q.x, s[0]);
+        s[1] = fma(q.w, q.y, s[1]);
+        s[2] = fma(q.w, q.z, s[2]);
+    }
+    uint32_t cur = b;
+    for (;;) {
+        Node &N = node[cur];
+        N.M = M;
+        for (int a = 0; a < 3; a++) {
+            S[a * nnmax + cur] = s[a];
+            N.com[a] = (M != 0.0) ? s[a] / M : N.blo[a] + 0.5 * N.l;
+        }
+        if (cur == 0) return;
+        uint32_t par = N.parent;
+        __threadfence();
+        uint32_t nchp = node[par].meta & 255u;
+        uint32_t old = atomicAdd(&arrive[par], 1u);
+        if (old != nchp - 1) return;
+        __threadfence();
+        uint32_t c0 = node[par].child;
+        M = 0.0;
+        s[0] = s[1] = s[2] = 0.0;
+        for (uint32_t k = 0; k < nchp; k++) {
+            M += __hip_atomic_load(&node[c0 + k].M, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            for (int a = 0; a < 3; a++)
+                s[a] += __hip_atomic_load(&S[a * nnmax + c0 + k], __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+        }
+        cur = par;
+    }
+}
+
+void launch_topology(BuildBufs &B, bool moments, hipStream_t s) {
+    int64_t n = B.n;
+    unsigned gb = (unsigned)((n + 255) / 256);
+    const uint64_t *key = B.key[0];
+    int8_t *dwin = (int8_t *)B.lvl_key2;   // scratch: reused as the level array later
+    hipLaunchKernelGGL(k_cpl, dim3(gb), dim3(256), 0, s, key, n, B.n_crit, B.cpl, dwin);
+    hipLaunchKernelGGL(k_leaflev, dim3(gb), dim3(256), 0, s, B.cpl, dwin, n, B.n_crit, B.leaflev,
+                       B.nstart);
+    launch_scan_u32(B.nstart, n + 1, B.scan_part, B.nn, s);
+    hipLaunchKernelGGL(k_emit_pre, dim3(gb), dim3(256), 0, s, key, B.cpl, B.nstart, n, B.pre_key,
+                       B.pre_val, B.pre_first, B.pre_count);
+    launch_radix_u32(B.pre_key, B.pre_val, B.lvl_key2, B.bfs2pre, B.hist, B.nn, B.nnmax, 0, s);
+    unsigned gn = (unsigned)((B.nnmax + 255) / 256);
+    hipLaunchKernelGGL(k_pre2bfs, dim3(gn), dim3(256), 0, s, B.bfs2pre, B.nn, B.pre2bfs);
+    hipLaunchKernelGGL(k_fill_nodes, dim3(gn), dim3(256), 0, s, key, B.leaflev, B.nstart,
+                       B.bfs2pre, B.pre2bfs, B.lvl_key2, B.pre_first, B.pre_count, B.nn, B.frame,
+                       B.invth2, B.node, B.arrive);
+    if (moments)
+        hipLaunchKernelGGL(k_moments, dim3(gn), dim3(256), 0, s, B.node, B.src, B.S, B.nn,
+                           B.nnmax, B.arrive);
+}
+
+}  // namespace htree

@@ -1,0 +1,179 @@
+// htree_dev.h -- device data structures and launch wrappers shared by the
+// HIP translation units of libhtree (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace htree {
+
+constexpr int kMaxLevel = 21;          // 63-bit keys: 21 levels of 3 bits
+constexpr int kWave = 64;
+
+// Build frame of one tree, written by the bounding-box kernel.
+struct Frame {
+    double lo[3];       // coordinate minimum
+    double side;        // root cube side, a power of two >= extent
+    double scale;       // 2^21 / side (exact power of two)
+    double R2pad2;      // (R2 + slack)^2 for conservative neighbour pruning
+};
+
+// One tree node in level (breadth-first) order; children of a node are
+// contiguous.  96 bytes, read as six 16-byte loads by the walks.
+struct alignas(16) Node {
+    double com[3];      // centre of mass, build frame
+    double M;           // mass
+    double blo[3];      // lower corner of the cell box, build frame (exact)
+    double l;           // cell side
+    double rb2;         // squared opening radius (l*l) / theta^2
+    uint32_t first;     // first particle (sorted position)
+    uint32_t count;     // number of particles
+    uint32_t child;     // index of the first child (internal nodes)
+    uint32_t meta;      // nchild | level << 8
+    uint32_t parent;    // index of the parent (root: itself)
+    uint32_t pad;
+};
+static_assert(sizeof(Node) == 96, "node record layout");
+
+
+// ---------------------------------------------------------------------------
+// wavefront helpers (wave64)
+// ---------------------------------------------------------------------------
+__device__ inline uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
+
+template <typename T>
+__device__ inline T wave_min(T v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+template <typename T>
+__device__ inline T wave_max(T v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ inline uint32_t wave_incl_scan(uint32_t v) {
+    const int lane = __lane_id();
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t t = __shfl_up(v, o);
+        if (lane >= o) v += t;
+    }
+    return v;
+}
+__device__ inline uint32_t wave_sum(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Launch-order block index -> work item, so that each of the eight XCDs
+// (which take workgroups round-robin) walks one contiguous run of items and
+// keeps its neighbouring groups' tree nodes in its own L2.
+__device__ inline int64_t xcd_item(int64_t bid, int64_t total) {
+    const int64_t nx = 8;
+    int64_t q = total / nx, r = total % nx;
+    int64_t x = bid % nx, s = bid / nx;
+    return x * q + (x < r ? x : r) + s;
+}
+
+// Sticky device status bits.
+enum : uint32_t { kStatusNonFinite = 1u, kStatusOverflow = 2u };
+
+// Radix-sort tile: 256 threads x 16 items.
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;
+
+inline int64_t sort_blocks(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+
+// Workspace slices for one tree build (device pointers).
+struct BuildBufs {
+    int64_t n;
+    int32_t n_crit;
+    double invth2;
+    double R2;
+    // particle state, two copies each; cur selects the live copy
+    double *x[2];          // [3][n]
+    float *v[2];           // [3][n]
+    float *m[2];           // [n]
+    uint32_t *perm[2];     // [n] sorted position -> caller index
+    float *as[2];          // [3][n] soft acceleration (sorted order)
+    float *ah[2];          // [3][n] hard acceleration
+    int cur;
+    double4 *src;          // [n] build-frame position and mass
+    uint64_t *key[2];      // [n] sort keys (ping-pong)
+    uint32_t *idx[2];      // [n] sort payload
+    uint32_t *hist;        // radix histograms
+    double *bbox_part;     // [nb][6]
+    Frame *frame;
+    uint32_t *status;      // sticky status word
+    // topology
+    int8_t *cpl;           // [n] common-prefix level with the previous key
+    int8_t *leaflev;       // [n] leaf level of each particle
+    uint32_t *nstart;      // [n+1] nodes starting at each position, scanned
+    uint32_t *scan_part;   // scan partials
+    uint32_t *nn;          // device node count
+    uint32_t *pre_key;     // [nnmax] level of each pre-order node
+    uint32_t *pre_val;     // [nnmax] pre-order index
+    uint32_t *lvl_key2;    // [nnmax] partitioned levels (scratch)
+    uint32_t *bfs2pre;     // [nnmax]
+    uint32_t *pre2bfs;     // [nnmax]
+    uint32_t *pre_first;   // [nnmax]
+    uint32_t *pre_count;   // [nnmax]
+    Node *node;            // [nnmax] level order
+    double *S;             // [3][nnmax] first mass moments
+    uint32_t *arrive;      // [nnmax] bottom-up arrival counters
+    int64_t nnmax;
+};
+
+// Host launch wrappers (build.hip).
+void launch_bbox_keys(const BuildBufs &B, hipStream_t s);
+void launch_sort(BuildBufs &B, hipStream_t s);
+void launch_gather(BuildBufs &B, hipStream_t s);
+void launch_topology(BuildBufs &B, bool moments, hipStream_t s);
+void launch_check_finite(const BuildBufs &B, hipStream_t s);
+void launch_radix_u32(uint32_t *key_in, uint32_t *val_in, uint32_t *key_out, uint32_t *val_out,
+                      uint32_t *hist, const uint32_t *count_dev, int64_t nmax, int shift,
+                      hipStream_t s);
+size_t scan_partials(int64_t n);
+void launch_scan_u32(uint32_t *data, int64_t n, uint32_t *part, uint32_t *total, hipStream_t s);
+
+// Force kernels (force.hip).
+struct ForceArgs {
+    const Node *node;
+    const double4 *src;       // sorted build-frame positions and masses
+    const double *x;          // [3][n] sorted FP64 positions (hard test)
+    const Frame *frame;
+    int64_t n;
+    int32_t g;                // group size (64)
+    int64_t n_groups;
+    float G, eps2;
+    float R2f, invdR;         // changeover: Y = (R2 - r) * invdR
+    double R2sq;              // exact contract radius squared
+    float *acc;               // [3][n] sorted order output
+    float *pot;               // [n] or null
+    int32_t *ngb;             // [n] or null
+    uint32_t *gcount;         // [3][n_groups] list sizes or null
+    unsigned long long *tally;  // [4] interaction tallies
+    uint32_t *status;
+};
+void launch_soft(const ForceArgs &A, bool hybrid, bool pot, hipStream_t s);
+void launch_hard(const ForceArgs &A, hipStream_t s);
+
+// Integrator and layout kernels (integrate.hip).
+void launch_kick_drift(double *x, float *v, const float *a1, float c1, const float *a2, float c2,
+                       double dt_drift, int64_t n, hipStream_t s);
+void launch_scatter3(const float *src_sorted, const uint32_t *perm, float *dst, int64_t n,
+                     hipStream_t s);
+void launch_scatter1f(const float *src_sorted, const uint32_t *perm, float *dst, int64_t n,
+                      hipStream_t s);
+void launch_scatter1i(const int32_t *src_sorted, const uint32_t *perm, int32_t *dst, int64_t n,
+                      hipStream_t s);
+void launch_gather3(const float *src_caller, const uint32_t *perm, float *dst_sorted, int64_t n,
+                    hipStream_t s);
+void launch_scatter_x(const double *x_sorted, const uint32_t *perm, double *dst, int64_t n,
+                      hipStream_t s);
+void launch_set_state(const double *x, const float *v, const float *m, double *xs, float *vs,
+                      float *ms, uint32_t *perm, int64_t n, hipStream_t s);
+void launch_add3(const float *a, const float *b, float *out, int64_t n, hipStream_t s);
+void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
+
+}  // namespace htree

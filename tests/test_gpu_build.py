@@ -1,0 +1,86 @@
+"""GPU tree build vs the oracle: keys, permutation, frame, topology and
+centres of mass must agree bit for bit."""
+import numpy as np
+import pytest
+
+import synth
+from tests._gpu import as_inputs, make_tree, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(name):
+    if name == "plummer4k":
+        return synth.plummer(4096, 1)
+    if name == "ragged1000":
+        return synth.plummer(1000, 41)
+    if name == "cube3001":
+        return synth.cold_cube(3001, 42)
+    if name == "tiny1":
+        return synth.plummer(1, 43)
+    if name == "small15":
+        return synth.plummer(15, 44)
+    if name == "dups":
+        x, v, m = synth.plummer(5000, 45)
+        x[:, 1000:1100] = x[:, 999:1000]       # 101 coincident particles: depth-21 leaves
+        return x, v, m
+    if name == "hernquist20k":
+        return synth.hernquist(20000, 46)
+    raise KeyError(name)
+
+
+CASES = ["plummer4k", "ragged1000", "cube3001", "tiny1", "small15", "dups", "hernquist20k"]
+
+
+@pytest.mark.parametrize("case", CASES)
+@pytest.mark.parametrize("n_crit", [16, 1, 5])
+def test_build_bit_exact(orc, case, n_crit):
+    torch, P = need_gpu()
+    x, v, m = _case(case)
+    x, v32, m32, v64, m64 = as_inputs(x, v, m)
+    print("case", case, "n_crit", n_crit, "n", x.shape[1], flush=True)
+    t = make_tree(P, torch, x, v32, m32, n_crit=n_crit, theta=0.6)
+    t.build_tree()
+    t.sync()
+    keys, perm, lo, side = t.export_keys()
+    T = orc.Tree(x, m64, n_crit=n_crit, theta=0.6)
+    olo, oside = T.frame()
+    operm, okey, ou = T.sorted()
+    assert np.array_equal(lo, olo) and side == oside
+    assert np.array_equal(keys, okey)
+    assert np.array_equal(perm.astype(np.int64), operm)
+    g = t.export_nodes()
+    o = T.nodes()
+    assert len(g["level"]) == T.nnodes
+    gk = np.lexsort((g["first"], g["level"]))
+    ok = np.lexsort((o["first"], o["level"]))
+    for f in ("level", "first", "count"):
+        assert np.array_equal(g[f][gk].astype(np.int64), o[f][ok].astype(np.int64)), f
+    assert np.array_equal(g["M"][gk], o["M"][ok])
+    assert np.array_equal(g["com"][:, gk], o["com"][:, ok])
+
+
+def test_build_deterministic():
+    torch, P = need_gpu()
+    x, v, m = synth.plummer(50000, 47)
+    x, v32, m32, _, _ = as_inputs(x, v, m)
+    out = []
+    for _ in range(2):
+        t = make_tree(P, torch, x, v32, m32)
+        t.build_tree()
+        t.sync()
+        out.append(t.export_nodes())
+    for f in out[0]:
+        assert np.array_equal(out[0][f], out[1][f])
+
+
+def test_nonfinite_input_reported():
+    torch, P = need_gpu()
+    x, v, m = synth.plummer(1000, 48)
+    x[1, 10] = np.nan
+    x, v32, m32, _, _ = as_inputs(x, v, m)
+    t = make_tree(P, torch, x, v32, m32)
+    t.build_tree()
+    with pytest.raises(P.HTreeError) as ei:
+        t.sync()
+    assert ei.value.code == P.HTREE_EINVAL

@@ -1,0 +1,126 @@
+"""GPU soft and hard forces vs the oracle on identical trees and lists.
+
+List sizes per group and neighbour counts must match bit for bit; forces
+are FP32 and must meet p99 relative error <= 1e-5 against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import synth
+from tests._gpu import as_inputs, make_tree, need_gpu, rel_err, report
+
+pytestmark = pytest.mark.gpu
+
+TOL_P99 = 1e-5
+
+
+def _wl(name):
+    if name == "plummer4k":
+        wl = synth.WORKLOADS["plummer4k"]
+        return wl.make(), wl.eps, wl.R1, wl.R2
+    if name == "ragged3001":
+        x = synth.plummer(3001, 51)
+        R2 = synth.r2_for_neighbours("plummer", 3001, 32)
+        return x, 1.0 / 64, R2 / 2, R2
+    if name == "cube5000":
+        x = synth.cold_cube(5000, 52)
+        R2 = synth.r2_for_neighbours("cube", 5000, 40)
+        return x, 0.02, R2 / 2, R2
+    raise KeyError(name)
+
+
+@pytest.mark.parametrize("name", ["plummer4k", "ragged3001", "cube5000"])
+@pytest.mark.parametrize("theta", [0.0, 0.5, 0.8])
+@pytest.mark.parametrize("hybrid", [0, 1])
+def test_soft_force_parity(orc, name, theta, hybrid):
+    torch, P = need_gpu()
+    (x, v, m), eps, R1, R2 = _wl(name)
+    x, v32, m32, v64, m64 = as_inputs(x, v, m)
+    n = x.shape[1]
+    print("soft", name, "theta", theta, "hybrid", hybrid, flush=True)
+    t = make_tree(P, torch, x, v32, m32, theta=theta, eps=eps, R1=R1, R2=R2, hybrid=hybrid,
+                  flags=P.F_POT)
+    t.build_tree()
+    acc, pot = t.soft_force(want_pot=True)
+    t.sync()
+    st = t.stats()
+    npc, nfar, nnear = t.group_counts()
+    T = orc.Tree(x, m64, n_crit=16, theta=theta)
+    opc, ofar, onear = T.walk_counts(64, R2, hybrid)
+    assert np.array_equal(npc, opc) and np.array_equal(nfar, ofar) and np.array_equal(nnear, onear)
+    oacc, opot, ointer = T.soft(64, 1.0, eps, R1, R2, hybrid, potential=True)
+    assert st["soft_interactions"] == ointer
+    e = rel_err(acc.cpu().numpy().astype(np.float64), oacc)
+    report("soft acc", e)
+    assert np.percentile(e, 99) <= TOL_P99
+    ep = np.abs(pot.cpu().numpy() - opot) / np.abs(opot)
+    report("soft pot", ep)
+    assert np.percentile(ep, 99) <= TOL_P99
+    if theta == 0.0 and not hybrid:
+        ref = orc.direct(x, m64, 1.0, eps)
+        assert np.percentile(rel_err(acc.cpu().numpy().astype(np.float64), ref), 99) <= TOL_P99
+
+
+@pytest.mark.parametrize("name", ["plummer4k", "ragged3001", "cube5000"])
+def test_hard_force_parity(orc, name):
+    torch, P = need_gpu()
+    (x, v, m), eps, R1, R2 = _wl(name)
+    x, v32, m32, v64, m64 = as_inputs(x, v, m)
+    print("hard", name, flush=True)
+    t = make_tree(P, torch, x, v32, m32, eps=eps, R1=R1, R2=R2)
+    t.build_tree()
+    ah, ngb = t.hard_force()
+    t.sync()
+    st = t.stats()
+    oah, _, ongb = orc.split_direct(x, m64, 1.0, eps, R1, R2, soft=False)
+    assert np.array_equal(ngb.cpu().numpy().astype(np.int64), ongb)
+    assert st["hard_pairs"] == ongb.sum()
+    e = rel_err(ah.cpu().numpy().astype(np.float64), oah)
+    report("hard acc", e[ongb > 0])
+    assert np.percentile(e[ongb > 0], 99) <= TOL_P99
+    assert np.all(ah.cpu().numpy()[:, ongb == 0] == 0)
+
+
+def test_soft_plus_hard_theta0_is_direct(orc):
+    torch, P = need_gpu()
+    (x, v, m), eps, R1, R2 = _wl("plummer4k")
+    x, v32, m32, v64, m64 = as_inputs(x, v, m)
+    t = make_tree(P, torch, x, v32, m32, theta=0.0, eps=eps, R1=R1, R2=R2)
+    t.build_tree()
+    a_s = t.soft_force()
+    a_h, _ = t.hard_force()
+    t.sync()
+    ref = orc.direct(x, m64, 1.0, eps)
+    e = rel_err((a_s + a_h).cpu().numpy().astype(np.float64), ref)
+    report("theta0 soft+hard vs direct", e)
+    assert np.percentile(e, 99) <= TOL_P99
+
+
+def test_forces_deterministic():
+    torch, P = need_gpu()
+    (x, v, m), eps, R1, R2 = _wl("plummer4k")
+    x, v32, m32, _, _ = as_inputs(x, v, m)
+    res = []
+    for _ in range(2):
+        t = make_tree(P, torch, x, v32, m32, eps=eps, R1=R1, R2=R2)
+        t.build_tree()
+        a = t.soft_force()
+        h, ngb = t.hard_force()
+        t.sync()
+        res.append((a.cpu().numpy(), h.cpu().numpy(), ngb.cpu().numpy()))
+    for u, w in zip(res[0], res[1]):
+        assert np.array_equal(u, w)
+
+
+def test_call_order_errors():
+    torch, P = need_gpu()
+    (x, v, m), eps, R1, R2 = _wl("plummer4k")
+    x, v32, m32, _, _ = as_inputs(x, v, m)
+    t = make_tree(P, torch, x, v32, m32, eps=eps, R1=R1, R2=R2)
+    with pytest.raises(P.HTreeError) as ei:
+        t.soft_force()
+    assert ei.value.code == P.HTREE_ESTATE
+    tp = make_tree(P, torch, x, v32, m32, hybrid=0)
+    tp.build_tree()
+    with pytest.raises(P.HTreeError) as ei:
+        tp.hard_force()
+    assert ei.value.code == P.HTREE_EINVAL
