@@ -55,7 +55,7 @@ typedef int32_t htree_status;
 
 typedef struct {
     double  G;            /* gravitational constant (> 0)                            */
-    double  eps;          /* Plummer softening length (> 0)                          */
+    double  eps;          /* Plummer softening length (>= 1e-15)                     */
     double  theta;        /* opening angle: a cell of side l is opened while the     */
                           /* group lies closer than l/theta; 0 opens every cell     */
     double  R1, R2;       /* changeover band, 0 < R1 < R2 (hybrid mode only)         */
@@ -76,7 +76,8 @@ typedef struct {
     int64_t soft_interactions;  /* sum over groups of sinks x entries               */
     int64_t hard_candidates;    /* sink-source pairs tested against R2              */
     int64_t hard_pairs;         /* accepted neighbour pairs (sum of ngb)            */
-    float   ms_build, ms_soft, ms_hard, ms_kick;  /* last call, with HTREE_F_TIMING */
+    float   ms_build, ms_soft, ms_hard, ms_kick;  /* summed, with HTREE_F_TIMING  */
+    int32_t calls_build, calls_soft, calls_hard, pad;
 } htree_counters;
 
 typedef struct htree_ctx htree_ctx;
@@ -143,11 +144,26 @@ htree_status htree_get_state(htree_ctx *ctx, double *d_x, float *d_v);
  * (HTREE_OK, or EINVAL for non-finite input, EOVERFLOW). */
 htree_status htree_sync(htree_ctx *ctx);
 
-/* Counters of the last build / force calls.  Synchronises the stream. */
+/* Counters summed over the build / force calls since the previous
+ * htree_stats call (or since htree_create), after which they restart from
+ * zero; n_nodes is that of the last build.  With HTREE_F_TIMING the ms_*
+ * fields are the summed HIP-event times of each phase on the context's
+ * stream.  Synchronises the stream. */
 htree_status htree_stats(htree_ctx *ctx, htree_counters *out);
 
+/* Sink groups of the last build (section III.A.2: sinks that share one
+ * traversal).  A group holds at most group_size particles inside one tree
+ * cell: a cell with at most group_size particles is a group; a bigger cell is
+ * split into its children; where all its children are small, consecutive
+ * children (octant order) are packed while the total stays <= group_size; a
+ * bigger leaf is cut into chunks.  htree_group_count returns their number (-1
+ * on error); htree_export_groups writes the count + 1 start positions (sorted
+ * order, the last one n) to a host array.  Both synchronise the stream. */
+int64_t htree_group_count(htree_ctx *ctx);
+htree_status htree_export_groups(htree_ctx *ctx, int32_t *starts);
+
 /* Per-group list sizes of the last soft_force: cells, far and near particle
- * entries (host arrays of htree_counters.n_groups int32 each; any may be NULL).
+ * entries (host arrays of htree_group_count int32 each; any may be NULL).
  * Synchronises the stream. */
 htree_status htree_group_counts(htree_ctx *ctx, int32_t *n_cells, int32_t *n_far,
                                 int32_t *n_near);

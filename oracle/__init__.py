@@ -61,10 +61,13 @@ def lib():
         L.orc_tree_frame.argtypes = [_p, _p, _p]
         L.orc_tree_sorted.argtypes = [_p, _p, _p, _p]
         L.orc_tree_nodes.argtypes = [_p] * 11
-        L.orc_walk_counts.argtypes = [_p, _i32, _f64, _i32, _p, _p, _p]
-        L.orc_walk_group.argtypes = [_p, _i32, _i64, _f64, _i32, _i64, _p, _p, _p, _p]
+        L.orc_tree_groups.restype = _i64
+        L.orc_tree_groups.argtypes = [_p, _i32]
+        L.orc_tree_group_starts.argtypes = [_p, _p]
+        L.orc_walk_counts.argtypes = [_p, _f64, _i32, _p, _p, _p]
+        L.orc_walk_group.argtypes = [_p, _i64, _f64, _i32, _i64, _p, _p, _p, _p]
         L.orc_soft.restype = _i64
-        L.orc_soft.argtypes = [_p, _i32, _f64, _f64, _f64, _f64, _i32, _i64, _p, _p, _p]
+        L.orc_soft.argtypes = [_p, _f64, _f64, _f64, _f64, _i32, _i64, _p, _p, _p]
         L.orc_step.argtypes = [_i64, _p, _p, _p, _f64, _f64, _f64, _f64, _f64, _i32, _i32,
                                _i32, _f64, _i32, _i32]
         _lib = L
@@ -135,7 +138,7 @@ def energy(x, v, m, G=1.0, eps=0.0):
 class Tree:
     """The oracle's octree over a particle set (built on construction)."""
 
-    def __init__(self, x, m, n_crit=16, theta=0.5):
+    def __init__(self, x, m, n_crit=16, theta=0.5, group=64):
         self.x = _f64c(x)
         self.m = _f64c(m)
         self.n = self.x.shape[1]
@@ -145,6 +148,8 @@ class Tree:
                                        self.theta)
         if not self._h:
             raise ValueError("oracle tree build rejected its arguments")
+        self.g = int(group)
+        self.ngroups = int(lib().orc_tree_groups(self._h, self.g))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -182,22 +187,27 @@ class Tree:
                                          "com", "blo", "l", "rb2")])
         return d
 
-    def walk_counts(self, g, R2, hybrid):
-        ng = (self.n + g - 1) // g
-        a = [np.zeros(ng, np.int64) for _ in range(3)]
-        lib().orc_walk_counts(self._h, g, R2, int(hybrid), *[_ptr(v) for v in a])
+    def group_starts(self):
+        """Start of each sink group in sorted order, plus n at the end."""
+        s = np.zeros(self.ngroups + 1, np.int64)
+        lib().orc_tree_group_starts(self._h, _ptr(s))
+        return s
+
+    def walk_counts(self, R2, hybrid):
+        a = [np.zeros(self.ngroups, np.int64) for _ in range(3)]
+        lib().orc_walk_counts(self._h, R2, int(hybrid), *[_ptr(v) for v in a])
         return tuple(a)
 
-    def walk_group(self, g, k, R2, hybrid, cap=1 << 20):
+    def walk_group(self, k, R2, hybrid, cap=1 << 20):
         cnt = np.zeros(3, np.int64)
         pc = np.zeros(cap, np.int64)
         far = np.zeros(cap, np.int64)
         near = np.zeros(cap, np.int64)
-        lib().orc_walk_group(self._h, g, k, R2, int(hybrid), cap, _ptr(pc), _ptr(far),
+        lib().orc_walk_group(self._h, k, R2, int(hybrid), cap, _ptr(pc), _ptr(far),
                              _ptr(near), _ptr(cnt))
         return pc[:cnt[0]].copy(), far[:cnt[1]].copy(), near[:cnt[2]].copy()
 
-    def soft(self, g, G, eps, R1, R2, hybrid, groups=None, potential=False):
+    def soft(self, G, eps, R1, R2, hybrid, groups=None, potential=False):
         """Soft (hybrid) or full (plain) tree force; returns (acc, pot, interactions).
 
         acc has shape (3, n) in caller order; sinks outside ``groups`` stay 0.
@@ -206,7 +216,7 @@ class Tree:
         pot = np.zeros(self.n) if potential else None
         gr = None if groups is None else np.ascontiguousarray(groups, dtype=np.int64)
         ngr = 0 if gr is None else gr.size
-        inter = lib().orc_soft(self._h, g, G, eps, R1, R2, int(hybrid), ngr, _ptr(gr),
+        inter = lib().orc_soft(self._h, G, eps, R1, R2, int(hybrid), ngr, _ptr(gr),
                                _ptr(acc), _ptr(pot))
         return acc, pot, int(inter)
 

@@ -255,6 +255,9 @@ typedef struct {
     double *m;                /* masses, sorted                            */
     onode *nd;
     int64_t nn, cap;
+    int64_t *gstart;          /* sink groups: [gstart[k], gstart[k+1]) in sorted order */
+    int64_t ng, gcap;
+    int32_t g;
 } orc_tree;
 
 typedef struct { uint64_t key; int64_t idx; } kv;
@@ -445,6 +448,7 @@ void orc_tree_free(orc_tree *T)
     if (!T) return;
     free(T->perm); free(T->key); free(T->q); free(T->u); free(T->x); free(T->m);
     free(T->nd);
+    free(T->gstart);
     free(T);
 }
 
@@ -485,6 +489,75 @@ void orc_tree_nodes(const orc_tree *T, int32_t *level, int64_t *first, int64_t *
         if (l) l[k] = c->l;
         if (rb2) rb2[k] = c->rb2;
     }
+}
+
+/* ===========================================================================
+ * Sink groups (section III.A.2: several sinks share one traversal; their
+ * positions must be close, which the key order provides)
+ * ========================================================================= */
+
+static void gpush(orc_tree *T, int64_t start)
+{
+    if (T->ng == T->gcap) {
+        T->gcap = T->gcap ? 2 * T->gcap : 1024;
+        T->gstart = (int64_t *)realloc(T->gstart, sizeof(int64_t) * (size_t)(T->gcap + 1));
+    }
+    T->gstart[T->ng++] = start;
+}
+
+/*
+ * Groups of at most g sorted particles, each inside one cell: a cell with at
+ * most g particles is one group; a cell with more is split into its
+ * children.  Where every child of a cell holds at most g particles,
+ * consecutive children (octant order) are packed into one group while the
+ * total stays <= g; where some child holds more, each small child is a group
+ * of its own (a run could otherwise span the big sibling's cell).  A leaf
+ * with more than g particles (only possible at the deepest level, or if
+ * n_crit > g) is cut into chunks of g.
+ */
+static void groups_rec(orc_tree *T, int64_t id, int64_t g)
+{
+    const onode *c = &T->nd[id];
+    if (c->count <= g) {
+        gpush(T, c->first);
+        return;
+    }
+    if (c->nchild == 0) {
+        for (int64_t s = c->first; s < c->first + c->count; s += g) gpush(T, s);
+        return;
+    }
+    int pack = 1;
+    for (int k = 0; k < c->nchild; k++)
+        if (T->nd[c->child[k]].count > g) pack = 0;
+    int64_t run = 0;
+    for (int k = 0; k < c->nchild; k++) {
+        int64_t ck = T->nd[id].child[k];
+        const onode *ch = &T->nd[ck];
+        if (ch->count > g) {
+            groups_rec(T, ck, g);
+        } else if (!pack) {
+            gpush(T, ch->first);
+        } else {
+            if (run > 0 && run + ch->count > g) run = 0;
+            if (run == 0) gpush(T, ch->first);
+            run += ch->count;
+        }
+    }
+}
+
+/* Builds the sink groups for group size g; returns their number. */
+int64_t orc_tree_groups(orc_tree *T, int32_t g)
+{
+    T->ng = 0;
+    T->g = g;
+    groups_rec(T, 0, g);
+    T->gstart[T->ng] = T->n;
+    return T->ng;
+}
+
+void orc_tree_group_starts(const orc_tree *T, int64_t *starts)
+{
+    memcpy(starts, T->gstart, sizeof(int64_t) * (size_t)(T->ng + 1));
 }
 
 /* ===========================================================================
@@ -580,17 +653,17 @@ static void walk(const orc_tree *T, int64_t id, const gbox *B, double R2sq, int 
 static void wl_free(wlist *L) { free(L->pc); free(L->far); free(L->near); }
 
 /*
- * Per-group list sizes for groups of g consecutive sorted particles:
- * n_pc cells, n_far and n_near source particles (self included).
+ * Per-group list sizes for the groups of orc_tree_groups: n_pc cells, n_far
+ * and n_near source particles (self included).
  */
-void orc_walk_counts(const orc_tree *T, int32_t g, double R2, int32_t hybrid,
+void orc_walk_counts(const orc_tree *T, double R2, int32_t hybrid,
                      int64_t *n_pc, int64_t *n_far, int64_t *n_near)
 {
-    int64_t ng = (T->n + g - 1) / g;
+    int64_t ng = T->ng;
     double R2sq = R2 * R2;
 #pragma omp parallel for schedule(dynamic, 4)
     for (int64_t k = 0; k < ng; k++) {
-        int64_t b = k * g, e = b + g < T->n ? b + g : T->n;
+        int64_t b = T->gstart[k], e = T->gstart[k + 1];
         gbox B;
         group_box(T, b, e, &B);
         wlist L;
@@ -605,10 +678,10 @@ void orc_walk_counts(const orc_tree *T, int32_t g, double R2, int32_t hybrid,
 
 /* Node-id lists of one group (for brute-force cross-checks); returns the three
  * counts in cnt[0..2] and writes up to cap ids into each non-NULL array. */
-void orc_walk_group(const orc_tree *T, int32_t g, int64_t k, double R2, int32_t hybrid,
+void orc_walk_group(const orc_tree *T, int64_t k, double R2, int32_t hybrid,
                     int64_t cap, int64_t *pc, int64_t *far, int64_t *near, int64_t *cnt)
 {
-    int64_t b = k * g, e = b + g < T->n ? b + g : T->n;
+    int64_t b = T->gstart[k], e = T->gstart[k + 1];
     gbox B;
     group_box(T, b, e, &B);
     wlist L;
@@ -624,7 +697,8 @@ void orc_walk_group(const orc_tree *T, int32_t g, int64_t k, double R2, int32_t 
 }
 
 /*
- * Soft force of the groups listed (all if groups == NULL), section II.C with
+ * Soft force of the groups listed (all if groups == NULL; groups as built by
+ * orc_tree_groups), section II.C with
  * the tree of section II.B:
  *   a_i = sum_cells G M_c (COM_c - u_i) / (d^2 + eps^2)^{3/2}
  *       + sum_far  j != i  G m_j (u_j - u_i) / (r^2 + eps^2)^{3/2}
@@ -634,18 +708,17 @@ void orc_walk_group(const orc_tree *T, int32_t g, int64_t k, double R2, int32_t 
  * Results go to acc[a*n + caller index] and pot[caller index]; the
  * interaction count (sinks times entries, self pairs included) is returned.
  */
-int64_t orc_soft(const orc_tree *T, int32_t g, double G, double eps, double R1, double R2,
+int64_t orc_soft(const orc_tree *T, double G, double eps, double R1, double R2,
                  int32_t hybrid, int64_t ngr, const int64_t *groups, double *acc, double *pot)
 {
     int64_t n = T->n;
-    int64_t ngall = (n + g - 1) / g;
-    if (!groups) ngr = ngall;
+    if (!groups) ngr = T->ng;
     double e2 = eps * eps, R2sq = R2 * R2;
     int64_t total = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : total)
     for (int64_t t = 0; t < ngr; t++) {
         int64_t k = groups ? groups[t] : t;
-        int64_t b = k * g, e = b + g < n ? b + g : n;
+        int64_t b = T->gstart[k], e = T->gstart[k + 1];
         gbox B;
         group_box(T, b, e, &B);
         wlist L;
@@ -703,7 +776,8 @@ static void forces(int64_t n, const double *x, const double *m, double G, double
                    double *a_s, double *a_h)
 {
     orc_tree *T = orc_tree_build(n, x, m, n_crit, theta);
-    orc_soft(T, g, G, eps, R1, R2, hybrid, 0, NULL, a_s, NULL);
+    orc_tree_groups(T, g);
+    orc_soft(T, G, eps, R1, R2, hybrid, 0, NULL, a_s, NULL);
     orc_tree_free(T);
     if (hybrid)
         orc_split_direct(n, x, m, G, eps, R1, R2, n, NULL, a_h, NULL, NULL);

@@ -141,9 +141,18 @@ class HTree:
         check(lib().htree_stats(self._h, C.byref(c)))
         return c.as_dict()
 
+    def group_starts(self):
+        import numpy as np
+        ng = int(lib().htree_group_count(self._h))
+        if ng < 0:
+            check(-5)
+        s = np.zeros(ng + 1, np.int32)
+        check(lib().htree_export_groups(self._h, C.c_void_p(s.ctypes.data)))
+        return s
+
     def group_counts(self):
         import numpy as np
-        ng = (self.n + self.params.group_size - 1) // self.params.group_size
+        ng = int(lib().htree_group_count(self._h))
         a = [np.zeros(ng, np.int32) for _ in range(3)]
         check(lib().htree_group_counts(self._h, *[C.c_void_p(v.ctypes.data) for v in a]))
         return tuple(a)

@@ -43,7 +43,8 @@ class Counters(C.Structure):
                 ("soft_near", C.c_int64), ("soft_interactions", C.c_int64),
                 ("hard_candidates", C.c_int64), ("hard_pairs", C.c_int64),
                 ("ms_build", C.c_float), ("ms_soft", C.c_float), ("ms_hard", C.c_float),
-                ("ms_kick", C.c_float)]
+                ("ms_kick", C.c_float), ("calls_build", C.c_int32), ("calls_soft", C.c_int32),
+                ("calls_hard", C.c_int32), ("pad", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -82,6 +83,9 @@ def lib() -> C.CDLL:
     L.htree_node_count.argtypes = [_p]
     L.htree_node_count.restype = C.c_int64
     L.htree_export_nodes.argtypes = [_p, _p, _p, _p, _p, _p]
+    L.htree_group_count.argtypes = [_p]
+    L.htree_group_count.restype = C.c_int64
+    L.htree_export_groups.argtypes = [_p, _p]
     L.htree_last_error.argtypes = []
     L.htree_last_error.restype = C.c_char_p
     L.htree_destroy.argtypes = [_p]
@@ -89,7 +93,7 @@ def lib() -> C.CDLL:
     for name in ("htree_create", "htree_set_state", "htree_build_tree", "htree_soft_force",
                  "htree_hard_force", "htree_kick_drift", "htree_step", "htree_get_state",
                  "htree_sync", "htree_stats", "htree_group_counts", "htree_export_keys",
-                 "htree_export_nodes"):
+                 "htree_export_nodes", "htree_export_groups"):
         getattr(L, name).restype = _st
     _lib = L
     return L

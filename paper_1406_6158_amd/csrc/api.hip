@@ -10,6 +10,7 @@
 #include <string.h>
 
 #include <string>
+#include <vector>
 
 using namespace htree;
 
@@ -43,7 +44,7 @@ htree_status validate(const htree_params *p, int64_t n) {
     if (!p) return fail(HTREE_EINVAL, "params is NULL");
     if (n < 1 || n > kMaxN) return fail(HTREE_EINVAL, "n = %lld outside [1, 2^27]", (long long)n);
     if (!is_fin(p->G) || p->G <= 0) return fail(HTREE_EINVAL, "G must be finite and > 0");
-    if (!is_fin(p->eps) || p->eps <= 0) return fail(HTREE_EINVAL, "eps must be finite and > 0");
+    if (!is_fin(p->eps) || p->eps < 1e-15) return fail(HTREE_EINVAL, "eps must be finite and >= 1e-15");
     if (!is_fin(p->theta) || p->theta < 0) return fail(HTREE_EINVAL, "theta must be >= 0");
     if (p->hybrid != 0 && p->hybrid != 1) return fail(HTREE_EINVAL, "hybrid must be 0 or 1");
     if (p->hybrid && !(is_fin(p->R1) && is_fin(p->R2) && p->R1 > 0 && p->R2 > p->R1))
@@ -85,14 +86,15 @@ struct htree_ctx {
     float *tmp3 = nullptr;             // [3][n] caller-order input staged in key order
     float *pot = nullptr;              // [n] key order
     int32_t *ngb = nullptr;            // [n] key order
-    uint32_t *gcount = nullptr;        // [3][ng]
+    uint32_t *gcount = nullptr;        // [3][n] list sizes per group (first ng used)
     unsigned long long *tally = nullptr;  // [4]
+    int n_wg = 0;                      // persistent force grid
     bool tree = false, moments = false, have_soft = false, have_hard = false;
     bool forces_current = false;
-    hipEvent_t ev[8] = {};
     bool timing = false;
-    float ms[4] = {0, 0, 0, 0};
-    bool ev_used[4] = {false, false, false, false};
+    std::vector<hipEvent_t> ev[3];     // per phase: start/end pairs since the last stats
+    int ev_n[3] = {0, 0, 0};
+    int calls[3] = {0, 0, 0};
 };
 
 namespace {
@@ -137,10 +139,12 @@ void carve(Carver &C, htree_ctx *c) {
     B.node = C.take<Node>(nnmax);
     B.S = C.take<double>(3 * nnmax);
     B.arrive = C.take<uint32_t>(nnmax);
+    B.gstart = C.take<uint32_t>(n + 1);
+    B.ng = C.take<uint32_t>(4);
     c->tmp3 = C.take<float>(3 * n);
     c->pot = C.take<float>(n);
     c->ngb = C.take<int32_t>(n);
-    c->gcount = C.take<uint32_t>(3 * c->ng);
+    c->gcount = C.take<uint32_t>(3 * n);
     c->tally = C.take<unsigned long long>(4);
 }
 
@@ -148,7 +152,6 @@ size_t footprint(const htree_params *p, int64_t n) {
     htree_ctx tmp;
     tmp.p = *p;
     tmp.n = n;
-    tmp.ng = (n + p->group_size - 1) / p->group_size;
     Carver C{nullptr};
     carve(C, &tmp);
     return (C.off + 255) & ~(size_t)255;
@@ -158,17 +161,22 @@ ForceArgs force_args(htree_ctx *c) {
     ForceArgs A;
     const BuildBufs &B = c->B;
     A.node = B.node;
+    A.gstart = B.gstart;
+    A.ng = B.ng;
     A.src = B.src;
     A.x = B.x[B.cur];
     A.frame = B.frame;
     A.n = c->n;
     A.g = c->p.group_size;
-    A.n_groups = c->ng;
     A.G = (float)c->p.G;
     A.eps2 = (float)(c->p.eps * c->p.eps);
     A.R2f = (float)c->p.R2;
     A.invdR = c->p.hybrid ? (float)(1.0 / (c->p.R2 - c->p.R1)) : 0.0f;
     A.R2sq = c->p.R2 * c->p.R2;
+    A.Gd = c->p.G;
+    A.eps2d = c->p.eps * c->p.eps;
+    A.R2d = c->p.R2;
+    A.invdR64 = c->p.hybrid ? 1.0 / (c->p.R2 - c->p.R1) : 0.0;
     A.acc = nullptr;
     A.pot = nullptr;
     A.ngb = nullptr;
@@ -179,13 +187,23 @@ ForceArgs force_args(htree_ctx *c) {
 }
 
 void ev_begin(htree_ctx *c, int k) {
-    if (c->timing) (void)hipEventRecord(c->ev[2 * k], c->stream);
+    c->calls[k]++;
+    if (!c->timing) return;
+    std::vector<hipEvent_t> &v = c->ev[k];
+    size_t need = 2 * (size_t)(c->ev_n[k] + 1);
+    while (v.size() < need) {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        v.push_back(e);
+    }
+    (void)hipEventRecord(v[2 * c->ev_n[k]], c->stream);
 }
 void ev_end(htree_ctx *c, int k) {
-    if (c->timing) {
-        (void)hipEventRecord(c->ev[2 * k + 1], c->stream);
-        c->ev_used[k] = true;
-    }
+    if (!c->timing) return;
+    std::vector<hipEvent_t> &v = c->ev[k];
+    if (v.size() < 2 * (size_t)(c->ev_n[k] + 1)) return;
+    (void)hipEventRecord(v[2 * c->ev_n[k] + 1], c->stream);
+    c->ev_n[k]++;
 }
 
 htree_status do_build(htree_ctx *c, bool moments) {
@@ -194,6 +212,7 @@ htree_status do_build(htree_ctx *c, bool moments) {
     launch_sort(c->B, c->stream);
     launch_gather(c->B, c->stream);
     launch_topology(c->B, moments, c->stream);
+    launch_groups(c->B, c->p.group_size, c->stream);
     ev_end(c, 0);
     HIP_OK(hipGetLastError());
     c->tree = true;
@@ -208,8 +227,7 @@ htree_status do_soft(htree_ctx *c) {
     const bool pot = (c->p.flags & HTREE_F_POT) != 0;
     A.pot = pot ? c->pot : nullptr;
     ev_begin(c, 1);
-    launch_zero_u32((uint32_t *)c->tally, 2, c->stream);
-    launch_soft(A, c->p.hybrid != 0, pot, c->stream);
+    launch_soft(A, c->p.hybrid != 0, pot, c->n_wg, c->stream);
     ev_end(c, 1);
     HIP_OK(hipGetLastError());
     c->have_soft = true;
@@ -223,8 +241,7 @@ htree_status do_hard(htree_ctx *c) {
     A.acc = c->B.ah[c->B.cur];
     A.ngb = c->ngb;
     ev_begin(c, 2);
-    launch_zero_u32((uint32_t *)(c->tally + 1), 4, c->stream);
-    launch_hard(A, c->stream);
+    launch_hard(A, c->n_wg, c->stream);
     ev_end(c, 2);
     HIP_OK(hipGetLastError());
     c->have_hard = true;
@@ -296,22 +313,27 @@ htree_status htree_create(htree_ctx **out, const htree_params *p, int64_t n, voi
     htree_ctx *c = new htree_ctx();
     c->p = *p;
     c->n = n;
-    c->ng = (n + p->group_size - 1) / p->group_size;
     c->stream = (hipStream_t)stream;
     hipError_t e = hipGetDevice(&c->device);
+    int cus = 0;
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device);
     if (e != hipSuccess) {
         delete c;
-        return fail(HTREE_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+        return fail(HTREE_EDEVICE, "device query: %s", hipGetErrorString(e));
     }
+    // persistent force kernels: as many one-wavefront workgroups as the CUs
+    // hold at once (LDS and VGPR use allow 16 per CU), a multiple of 8
+    c->n_wg = (cus > 0 ? cus : 256) * 16;
+    c->n_wg -= c->n_wg % 8;
     Carver C{(char *)ws};
     carve(C, c);
     c->B.invth2 = 1.0 / (p->theta * p->theta);
     c->B.R2 = p->hybrid ? p->R2 : 0.0;
     c->B.cur = 0;
     c->timing = (p->flags & HTREE_F_TIMING) != 0;
-    if (c->timing)
-        for (int k = 0; k < 8; k++) (void)hipEventCreate(&c->ev[k]);
     launch_zero_u32(c->B.status, 4, c->stream);
+    launch_zero_u32((uint32_t *)c->tally, 8, c->stream);
     launch_zero_u32(c->B.nn, 4, c->stream);
     e = hipGetLastError();
     if (e != hipSuccess) {
@@ -443,20 +465,25 @@ htree_status htree_stats(htree_ctx *c, htree_counters *out) {
     if (!out) return fail(HTREE_EINVAL, "out is NULL");
     HIP_OK(hipStreamSynchronize(c->stream));
     unsigned long long t[4];
-    uint32_t nn = 0;
+    uint32_t nn = 0, ng = 0;
     HIP_OK(hipMemcpy(t, c->tally, sizeof t, hipMemcpyDeviceToHost));
     HIP_OK(hipMemcpy(&nn, c->B.nn, sizeof nn, hipMemcpyDeviceToHost));
+    HIP_OK(hipMemcpy(&ng, c->B.ng, sizeof ng, hipMemcpyDeviceToHost));
+    c->ng = ng;
     memset(out, 0, sizeof *out);
     out->n = c->n;
-    out->n_groups = c->ng;
+    out->n_groups = ng;
     out->n_nodes = nn;
     out->soft_interactions = (int64_t)t[0];
     out->hard_candidates = (int64_t)t[1];
     out->hard_pairs = (int64_t)t[2];
     if (c->have_soft) {
-        int64_t ng = c->ng;
-        uint32_t *h = new uint32_t[3 * ng];
-        hipError_t e = hipMemcpy(h, c->gcount, sizeof(uint32_t) * 3 * ng, hipMemcpyDeviceToHost);
+        const int64_t n = c->n;
+        uint32_t *h = new uint32_t[3 * (size_t)ng + 1];
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < 3 && e == hipSuccess; k++)
+            e = hipMemcpy(h + k * (size_t)ng, c->gcount + k * n, sizeof(uint32_t) * ng,
+                          hipMemcpyDeviceToHost);
         if (e == hipSuccess)
             for (int64_t k = 0; k < ng; k++) {
                 out->soft_cells += h[k];
@@ -466,11 +493,23 @@ htree_status htree_stats(htree_ctx *c, htree_counters *out) {
         delete[] h;
         HIP_OK(e);
     }
-    if (c->timing) {
-        float *dst[3] = {&out->ms_build, &out->ms_soft, &out->ms_hard};
-        for (int k = 0; k < 3; k++)
-            if (c->ev_used[k]) HIP_OK(hipEventElapsedTime(dst[k], c->ev[2 * k], c->ev[2 * k + 1]));
+    float *dst[3] = {&out->ms_build, &out->ms_soft, &out->ms_hard};
+    for (int k = 0; k < 3; k++) {
+        float tot = 0.f;
+        for (int j = 0; j < c->ev_n[k]; j++) {
+            float ms = 0.f;
+            HIP_OK(hipEventElapsedTime(&ms, c->ev[k][2 * j], c->ev[k][2 * j + 1]));
+            tot += ms;
+        }
+        *dst[k] = tot;
+        c->ev_n[k] = 0;
     }
+    out->calls_build = c->calls[0];
+    out->calls_soft = c->calls[1];
+    out->calls_hard = c->calls[2];
+    c->calls[0] = c->calls[1] = c->calls[2] = 0;
+    launch_zero_u32((uint32_t *)c->tally, 8, c->stream);
+    HIP_OK(hipGetLastError());
     return HTREE_OK;
 }
 
@@ -478,10 +517,12 @@ htree_status htree_group_counts(htree_ctx *c, int32_t *n_cells, int32_t *n_far, 
     CTX_CHECK(c);
     if (!c->have_soft) return fail(HTREE_ESTATE, "no soft_force has run");
     HIP_OK(hipStreamSynchronize(c->stream));
+    uint32_t ng = 0;
+    HIP_OK(hipMemcpy(&ng, c->B.ng, sizeof ng, hipMemcpyDeviceToHost));
     int32_t *dst[3] = {n_cells, n_far, n_near};
     for (int k = 0; k < 3; k++)
         if (dst[k])
-            HIP_OK(hipMemcpy(dst[k], c->gcount + k * c->ng, sizeof(int32_t) * c->ng,
+            HIP_OK(hipMemcpy(dst[k], c->gcount + k * c->n, sizeof(int32_t) * ng,
                              hipMemcpyDeviceToHost));
     return HTREE_OK;
 }
@@ -536,14 +577,32 @@ htree_status htree_export_nodes(htree_ctx *c, int32_t *level, int32_t *first, in
     return HTREE_OK;
 }
 
+int64_t htree_group_count(htree_ctx *c) {
+    if (!c || !c->tree) return -1;
+    if (hipSetDevice(c->device) != hipSuccess) return -1;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return -1;
+    uint32_t ng = 0;
+    if (hipMemcpy(&ng, c->B.ng, sizeof ng, hipMemcpyDeviceToHost) != hipSuccess) return -1;
+    return ng;
+}
+
+htree_status htree_export_groups(htree_ctx *c, int32_t *starts) {
+    CTX_CHECK(c);
+    if (!c->tree) return fail(HTREE_ESTATE, "no current tree");
+    int64_t ng = htree_group_count(c);
+    if (ng < 0) return fail(HTREE_EDEVICE, "cannot read the group count");
+    if (starts)
+        HIP_OK(hipMemcpy(starts, c->B.gstart, sizeof(int32_t) * (ng + 1), hipMemcpyDeviceToHost));
+    return HTREE_OK;
+}
+
 const char *htree_last_error(void) { return g_err.c_str(); }
 
 void htree_destroy(htree_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
-    if (c->timing)
-        for (int k = 0; k < 8; k++)
-            if (c->ev[k]) (void)hipEventDestroy(c->ev[k]);
+    for (int k = 0; k < 3; k++)
+        for (hipEvent_t e : c->ev[k]) (void)hipEventDestroy(e);
     delete c;
 }
 

@@ -554,3 +554,65 @@ void launch_topology(BuildBufs &B, bool moments, hipStream_t s) {
 }
 
 }  // namespace htree
+
+namespace htree {
+
+// ---------------------------------------------------------------------------
+// sink groups (the same rule as the tree contract): a cell with at most g
+// particles is a group; a bigger cell is split into its children; where all
+// children are small, consecutive children are packed while the total stays
+// <= g; a bigger leaf is cut into chunks of g.  Each node with more than g
+// particles marks the group starts among its own children; a scan turns the
+// marks into the group start table.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_group_marks(const Node *node, const uint32_t *nn_dev,
+                                                     uint32_t g, uint32_t *flag) {
+    uint32_t b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= *nn_dev) return;
+    const Node &N = node[b];
+    uint32_t count = N.count, nch = N.meta & 255u;
+    if (count <= g) {
+        if (b == 0) flag[0] = 1u;       // the root is the only group
+        return;
+    }
+    if (nch == 0) {
+        for (uint32_t s = 0; s < count; s += g) flag[N.first + s] = 1u;
+        return;
+    }
+    bool pack = true;
+    for (uint32_t k = 0; k < nch; k++) pack &= node[N.child + k].count <= g;
+    uint32_t run = 0;
+    for (uint32_t k = 0; k < nch; k++) {
+        const Node &C = node[N.child + k];
+        if (C.count > g) continue;      // split by its own thread
+        if (!pack) {
+            flag[C.first] = 1u;
+            continue;
+        }
+        if (run > 0 && run + C.count > g) run = 0;
+        if (run == 0) flag[C.first] = 1u;
+        run += C.count;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_group_compact(const uint32_t *scan, int64_t n,
+                                                       uint32_t *gstart) {
+    int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    uint32_t s = scan[i];
+    if (scan[i + 1] != s) gstart[s] = (uint32_t)i;
+    if (i == n - 1) gstart[scan[n]] = (uint32_t)n;
+}
+
+void launch_groups(BuildBufs &B, int g, hipStream_t s) {
+    int64_t n = B.n;
+    uint32_t *flag = B.nstart;    // free once the topology is built
+    launch_zero_u32(flag, n + 1, s);
+    unsigned gn = (unsigned)((B.nnmax + 255) / 256);
+    hipLaunchKernelGGL(k_group_marks, dim3(gn), dim3(256), 0, s, B.node, B.nn, (uint32_t)g, flag);
+    launch_scan_u32(flag, n + 1, B.scan_part, B.ng, s);
+    hipLaunchKernelGGL(k_group_compact, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, flag, n,
+                       B.gstart);
+}
+
+}  // namespace htree

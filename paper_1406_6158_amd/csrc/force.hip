@@ -1,37 +1,43 @@
 // force.hip -- soft (tree) and hard (neighbour) force kernels for gfx950.
 //
 // Soft force (section II.B walk, grouped sinks of section III.A.2, split of
-// section II.C).  One wavefront serves one group of 64 consecutive
-// key-ordered sinks, one sink per lane.  The walk is wide depth-first: each
-// step pops up to 64 nodes from an LDS stack, one per lane, and tests them in
-// FP64 against the group's bounding box:
+// section II.C).  One wavefront serves one sink group (at most 64 sinks that
+// share a tree cell), one sink per lane.  The walk is wide depth-first over a
+// stack of child ranges (first node, count) in LDS: each step takes up to 64
+// nodes from the top ranges, one per lane, and tests them in FP64 against the
+// group's bounding box:
 //   D1 = dist^2(box_g, COM),  D2 = dist^2(box_g, cell box)
 //   accepted iff D1 >= r_b^2 and (hybrid ? D2 >= R2^2 : D2 > 0).
 // Accepted cells become particle-cell sources, rejected leaves particle
 // sources ("near", weighted by 1 - K, iff hybrid and D2 < R2^2), other nodes
-// push their (contiguous) children.  Sources are staged in LDS as FP32
-// offsets from the group centre plus mass; every 64 of them all lanes run the
-// interaction loop, FP32 per tile, tiles merged with compensated (Kahan)
+// push the range of their (contiguous) children.  Sources are staged in LDS as
+// FP32 offsets from the group centre plus mass; every 64 of them all lanes run
+// the interaction loop, FP32 per tile, tiles merged with compensated (Kahan)
 // summation.  No list leaves the chip.
 //
-// The stack stays bounded: a step that pops p nodes grows the stack by at
-// most 7p, so p is capped to keep a reserve of 160 entries; once the reserve
-// is reached the walk proceeds one node at a time, depth first, which adds at
-// most 7 entries per level on the current path (7 x 21 = 147).
+// The stack stays bounded: every popped node pushes at most one range, so a
+// step may take `want` nodes only while top + want leaves a reserve of 22
+// entries; past that the walk takes one node at a time, depth first, which
+// keeps at most one partial range per tree level (21).
+//
+// The kernels are persistent: a fixed grid (a multiple of 8 workgroups) loops
+// over the groups on a static schedule that keeps each XCD on one contiguous
+// range of groups, so neighbouring groups share tree nodes in that XCD's L2.
 //
 // Hard force (section II.C, eq. 10): per group, a walk that opens every node
 // whose box lies within R2 (plus rounding slack) of the group box collects
-// candidate leaves; each candidate pair is decided by the exact FP64 test
+// candidate leaves; their particles are filtered against the group box, then
+// every candidate pair is decided by the exact FP64 test
 // fma(dz,dz, fma(dy,dy, dx*dx)) < R2^2 on the master positions, and accepted
-// pairs add K(r) times the softened pair force in FP32.
+// pairs add K(r) times the softened pair force, summed in FP64.
 #include "htree_dev.h"
 
 #include <math.h>
 
 namespace htree {
 
-constexpr int kStk = 1024;
-constexpr int kStkReserve = 160;
+constexpr int kStk = 512;          // range entries
+constexpr int kStkReserve = 22;    // depth-first progress room (one range per level)
 constexpr int kPC = 128;
 constexpr int kRQ = 128;
 
@@ -66,28 +72,49 @@ __device__ inline float one_minus_K(float r, float R2f, float invdR) {
     float t = fmaf(fmaf(6.0f, w, -15.0f), w, 10.0f);
     return t * (w * w * w);
 }
-__device__ inline float K_of(float r, float R2f, float invdR) {
-    float Y = (R2f - r) * invdR;
-    Y = fminf(fmaxf(Y, 0.0f), 1.0f);
-    float s = Y * Y;
-    float t = fmaf(fmaf(6.0f, s, -15.0f), s, 10.0f);
+
+__device__ inline double rsqrt64(double s) {
+    double y = (double)rsq((float)s);
+    y = y * fma(-0.5 * s, y * y, 1.5);
+    y = y * fma(-0.5 * s, y * y, 1.5);
+    return y;
+}
+__device__ inline double K_of64(double r, double R2, double invdR) {
+    double Y = (R2 - r) * invdR;
+    Y = fmin(fmax(Y, 0.0), 1.0);
+    double s = Y * Y;
+    double t = fma(fma(6.0, s, -15.0), s, 10.0);
     return t * (s * s * s);
+}
+
+// Static schedule of the persistent kernels.  The grid is a multiple of 8
+// workgroups; workgroup b sits on XCD b % 8 (the dispatcher deals workgroups
+// to the XCDs round-robin) and takes, from that XCD's contiguous share of the
+// groups, every (grid / 8)-th group starting at slot b / 8.  The group index
+// is a function of scalar values only, so the loop is wave-uniform.
+__device__ inline uint32_t static_group(uint32_t k, uint32_t ng) {
+    const uint32_t nx = 8, x = blockIdx.x & 7u, slot = blockIdx.x >> 3;
+    const uint32_t slots = gridDim.x >> 3;
+    const uint32_t q = ng / nx, r = ng % nx;
+    const uint32_t size = q + (x < r ? 1u : 0u);
+    const uint32_t start = x * q + (x < r ? x : r);
+    const uint32_t off = slot + k * slots;
+    return off < size ? start + off : ng;
 }
 
 // Group setup shared by both walks.
 struct GroupCtx {
-    int64_t b0;
+    uint32_t b0;
     int ns;
     bool act;
     double lo[3], hi[3], c[3];
 };
 
-__device__ inline void group_setup(const double4 *src, int64_t n, int g, int64_t grp,
+__device__ inline void group_setup(const double4 *src, const uint32_t *gstart, uint32_t grp,
                                    GroupCtx &G, double4 &me) {
-    const int lane = threadIdx.x;
-    G.b0 = grp * g;
-    int64_t e0 = G.b0 + g < n ? G.b0 + g : n;
-    G.ns = (int)(e0 - G.b0);
+    const int lane = __lane_id();
+    G.b0 = gstart[grp];
+    G.ns = (int)(gstart[grp + 1] - G.b0);
     G.act = lane < G.ns;
     me = src[G.act ? G.b0 + lane : G.b0];
     double p[3] = {me.x, me.y, me.z};
@@ -154,23 +181,20 @@ __device__ inline void eval_near(const float4 *t, int cnt, float sx, float sy, f
     if (POT) kahan(A.p, A.pc, ph);
 }
 
-// Takes `want` particles from the top of a leaf-range stack (first[], cnt[],
-// nr ranges), consuming each range from its end, and returns for this lane
-// (lane < want) the sorted particle index.  Updates nr and the partially
-// consumed range.  All lanes must call it.
-__device__ inline uint32_t take_particles(uint32_t *first, uint32_t *cnt, int &nr, int want,
-                                          uint32_t *scan) {
-    const int lane = threadIdx.x;
+// Takes `want` items from the top of a range stack (first[], cnt[], nr
+// ranges, each count >= 1, the top 64 ranges holding at least `want` items),
+// consuming each range from its end.  Returns this lane's item (lane < want).
+// All lanes must call it.
+__device__ inline uint32_t take_items(uint32_t *first, uint32_t *cnt, int &nr, int want,
+                                      uint32_t *scan) {
+    const int lane = __lane_id();
+    HT_CHECK(want >= 1 && want <= 64 && nr >= 1);
     int r = nr < 64 ? nr : 64;
-    uint32_t ck = 0, fk = 0;
-    if (lane < r) {
-        ck = cnt[nr - 1 - lane];
-        fk = first[nr - 1 - lane];
-    }
+    uint32_t ck = lane < r ? cnt[nr - 1 - lane] : 0u;
     uint32_t inc = wave_incl_scan(ck);
     scan[lane] = inc;
     __syncthreads();
-    uint32_t pidx = 0;
+    uint32_t item = 0;
     if (lane < want) {
         int lo = 0, hi = r - 1;
         while (lo < hi) {
@@ -179,8 +203,9 @@ __device__ inline uint32_t take_particles(uint32_t *first, uint32_t *cnt, int &n
         }
         uint32_t prev = lo ? scan[lo - 1] : 0u;
         uint32_t f = first[nr - 1 - lo], c = cnt[nr - 1 - lo];
-        pidx = f + c - 1u - ((uint32_t)lane - prev);
+        item = f + c - 1u - ((uint32_t)lane - prev);
     }
+    HT_CHECK(__shfl(inc, r - 1) >= (uint32_t)want);
     uint64_t full = __ballot(lane < r && inc <= (uint32_t)want);
     int nfull = __popcll(full);
     uint32_t used = nfull ? __shfl(inc, nfull - 1) : 0u;
@@ -188,14 +213,23 @@ __device__ inline uint32_t take_particles(uint32_t *first, uint32_t *cnt, int &n
     if (lane == 0 && (uint32_t)want > used) cnt[nr - 1 - nfull] -= (uint32_t)want - used;
     nr -= nfull;
     __syncthreads();
-    return pidx;
+    return item;
+}
+
+// Number of nodes a walk step may take: up to 64, keeping room for one pushed
+// range per popped node plus the depth-first reserve.
+__device__ inline int step_width(int top, uint32_t avail) {
+    int w = avail < 64u ? (int)avail : 64;
+    int room = kStk - kStkReserve - top;
+    if (w > room) w = room > 1 ? room : 1;
+    return w;
 }
 
 // ---------------------------------------------------------------------------
 // soft force
 // ---------------------------------------------------------------------------
 struct SoftLDS {
-    uint32_t stk[kStk];
+    uint32_t sfirst[kStk], scnt[kStk];
     float4 pc[kPC];
     float4 tile[64];
     uint32_t ffirst[kRQ], fcnt[kRQ];
@@ -204,14 +238,12 @@ struct SoftLDS {
 };
 
 template <bool HYBRID, bool POT>
-__global__ __launch_bounds__(64) void k_soft(ForceArgs A) {
-    __shared__ SoftLDS S;
-    const int lane = threadIdx.x;
+__device__ void soft_group(const ForceArgs &A, SoftLDS &S, uint32_t grp) {
+    const int lane = __lane_id();
     const uint64_t lt = lanemask_lt();
-    const int64_t grp = xcd_item(blockIdx.x, A.n_groups);
     GroupCtx G;
     double4 me;
-    group_setup(A.src, A.n, A.g, grp, G, me);
+    group_setup(A.src, A.gstart, grp, G, me);
     const float sx = (float)(me.x - G.c[0]);
     const float sy = (float)(me.y - G.c[1]);
     const float sz = (float)(me.z - G.c[2]);
@@ -221,18 +253,18 @@ __global__ __launch_bounds__(64) void k_soft(ForceArgs A) {
     Acc acc = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, 0.f, 0.f};
     uint32_t n_pc = 0, n_far = 0, n_near = 0;
     int top = 1, npc = 0, nfr = 0, nnr = 0;
-    uint32_t ftot = 0, ntot = 0;
-    if (lane == 0) S.stk[0] = 0;
+    uint32_t avail = 1, ftot = 0, ntot = 0;
+    if (lane == 0) {
+        S.sfirst[0] = 0;
+        S.scnt[0] = 1;
+    }
     __syncthreads();
 
-    while (top > 0) {
-        int p = top < 64 ? top : 64;
-        int pmax = (kStk - kStkReserve - top) / 7;
-        if (p > pmax) p = pmax > 1 ? pmax : 1;
-        const bool have = lane < p;
-        uint32_t id = have ? S.stk[top - p + lane] : 0u;
-        top -= p;
-        __syncthreads();
+    while (avail > 0) {
+        const int want = step_width(top, avail);
+        uint32_t id = take_items(S.sfirst, S.scnt, top, want, S.scan);
+        avail -= (uint32_t)want;
+        const bool have = lane < want;
 
         bool acc_c = false, leaf = false, opn = false, nr = false;
         uint32_t first = 0, count = 0, child = 0, nch = 0;
@@ -287,14 +319,16 @@ __global__ __launch_bounds__(64) void k_soft(ForceArgs A) {
             ntot += cn;
             n_near += cn;
         }
-        // opened cells -> push children
-        uint32_t k = opn ? nch : 0u;
-        uint32_t inc = wave_incl_scan(k);
+        // opened cells -> push their child ranges
+        m = __ballot(opn);
         if (opn) {
-            uint32_t b = (uint32_t)top + inc - k;
-            for (uint32_t j = 0; j < k; j++) S.stk[b + j] = child + j;
+            int o = top + __popcll(m & lt);
+            S.sfirst[o] = child;
+            S.scnt[o] = nch;
         }
-        top += (int)__shfl(inc, 63);
+        top += __popcll(m);
+        avail += wave_sum(opn ? nch : 0u);
+        HT_CHECK(top <= kStk && npc < kPC && nfr < kRQ && nnr < kRQ);
         __syncthreads();
 
         while (npc >= 64) {
@@ -302,7 +336,7 @@ __global__ __launch_bounds__(64) void k_soft(ForceArgs A) {
             npc -= 64;
         }
         while (ftot >= 64) {
-            uint32_t pi = take_particles(S.ffirst, S.fcnt, nfr, 64, S.scan);
+            uint32_t pi = take_items(S.ffirst, S.fcnt, nfr, 64, S.scan);
             double4 q = A.src[pi];
             S.tile[lane] = make_float4((float)(q.x - G.c[0]), (float)(q.y - G.c[1]),
                                        (float)(q.z - G.c[2]), (float)q.w);
@@ -313,7 +347,7 @@ __global__ __launch_bounds__(64) void k_soft(ForceArgs A) {
         }
         if (HYBRID) {
             while (ntot >= 64) {
-                uint32_t pi = take_particles(S.nfirst, S.ncnt, nnr, 64, S.scan);
+                uint32_t pi = take_items(S.nfirst, S.ncnt, nnr, 64, S.scan);
                 double4 q = A.src[pi];
                 S.tile[lane] = make_float4((float)(q.x - G.c[0]), (float)(q.y - G.c[1]),
                                            (float)(q.z - G.c[2]), (float)q.w);
@@ -328,7 +362,7 @@ __global__ __launch_bounds__(64) void k_soft(ForceArgs A) {
     if (npc > 0) eval_far<POT, 0>(S.pc, npc, sx, sy, sz, eps2, acc);
     if (ftot > 0) {
         int want = (int)ftot;
-        uint32_t pi = take_particles(S.ffirst, S.fcnt, nfr, want, S.scan);
+        uint32_t pi = take_items(S.ffirst, S.fcnt, nfr, want, S.scan);
         if (lane < want) {
             double4 q = A.src[pi];
             S.tile[lane] = make_float4((float)(q.x - G.c[0]), (float)(q.y - G.c[1]),
@@ -340,7 +374,7 @@ __global__ __launch_bounds__(64) void k_soft(ForceArgs A) {
     }
     if (HYBRID && ntot > 0) {
         int want = (int)ntot;
-        uint32_t pi = take_particles(S.nfirst, S.ncnt, nnr, want, S.scan);
+        uint32_t pi = take_items(S.nfirst, S.ncnt, nnr, want, S.scan);
         if (lane < want) {
             double4 q = A.src[pi];
             S.tile[lane] = make_float4((float)(q.x - G.c[0]), (float)(q.y - G.c[1]),
@@ -348,6 +382,7 @@ __global__ __launch_bounds__(64) void k_soft(ForceArgs A) {
         }
         __syncthreads();
         eval_near<POT>(S.tile, want, sx, sy, sz, eps2, A.R2f, A.invdR, acc);
+        __syncthreads();
     }
 
     if (G.act) {
@@ -365,16 +400,28 @@ __global__ __launch_bounds__(64) void k_soft(ForceArgs A) {
     if (lane == 0) {
         if (A.gcount) {
             A.gcount[grp] = n_pc;
-            A.gcount[A.n_groups + grp] = n_far;
-            A.gcount[2 * A.n_groups + grp] = n_near;
+            A.gcount[A.n + grp] = n_far;
+            A.gcount[2 * A.n + grp] = n_near;
         }
         unsigned long long ent = (unsigned long long)n_pc + n_far + n_near;
         atomicAdd(&A.tally[0], (unsigned long long)G.ns * ent);
     }
 }
 
-void launch_soft(const ForceArgs &A, bool hybrid, bool pot, hipStream_t s) {
-    dim3 grid((unsigned)A.n_groups), block(64);
+template <bool HYBRID, bool POT>
+__global__ __launch_bounds__(64) void k_soft(ForceArgs A) {
+    __shared__ SoftLDS S;
+    const uint32_t ng = *A.ng;
+    for (uint32_t k = 0;; k++) {
+        const uint32_t grp = static_group(k, ng);
+        if (grp >= ng) break;
+        HT_CHECK(A.gstart[grp + 1] > A.gstart[grp] && A.gstart[grp + 1] - A.gstart[grp] <= 64);
+        soft_group<HYBRID, POT>(A, S, grp);
+    }
+}
+
+void launch_soft(const ForceArgs &A, bool hybrid, bool pot, int n_wg, hipStream_t s) {
+    dim3 grid((unsigned)n_wg), block(64);
     if (hybrid) {
         if (pot) hipLaunchKernelGGL((k_soft<true, true>), grid, block, 0, s, A);
         else hipLaunchKernelGGL((k_soft<true, false>), grid, block, 0, s, A);
@@ -387,87 +434,104 @@ void launch_soft(const ForceArgs &A, bool hybrid, bool pot, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // hard force
 // ---------------------------------------------------------------------------
+constexpr int kStage = 128;
+
 struct HardLDS {
-    uint32_t stk[kStk];
-    double tx[64], ty[64], tz[64];
-    float tm[64];
-    uint32_t ti[64];
+    uint32_t sfirst[kStk], scnt[kStk];
+    double tx[kStage], ty[kStage], tz[kStage];
+    float tm[kStage];
+    uint32_t ti[kStage];
     uint32_t rfirst[kRQ], rcnt[kRQ];
     uint32_t scan[64];
 };
 
-__global__ __launch_bounds__(64) void k_hard(ForceArgs A) {
-    __shared__ HardLDS S;
-    const int lane = threadIdx.x;
+__device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
+    const int lane = __lane_id();
     const uint64_t lt = lanemask_lt();
-    const int64_t grp = xcd_item(blockIdx.x, A.n_groups);
     GroupCtx G;
     double4 me;
-    group_setup(A.src, A.n, A.g, grp, G, me);
+    group_setup(A.src, A.gstart, grp, G, me);
     const int64_t n = A.n;
-    const int64_t mi = G.act ? G.b0 + lane : G.b0;
+    const uint32_t mi = G.act ? G.b0 + lane : G.b0;
     const double xi = A.x[mi], yi = A.x[n + mi], zi = A.x[2 * n + mi];
-    const uint32_t myidx = (uint32_t)mi;
     const double R2sq = A.R2sq;
     const double pad2 = A.frame->R2pad2;
-    const float eps2 = A.eps2, R2f = A.R2f, invdR = A.invdR;
+    const double eps2d = A.eps2d, R2 = A.R2d, invdR64 = A.invdR64;
 
-    Acc acc = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, 0.f, 0.f};
+    // Accepted pairs are summed in FP64: the neighbour sum cancels strongly
+    // (neighbours surround the sink), so FP32 per-pair rounding would be
+    // magnified; FP64 FMA issues at the FP32 rate on this chip and accepted
+    // pairs are few.  1/sqrt is an FP32 seed refined by two Newton steps.
+    double hx = 0.0, hy = 0.0, hz = 0.0;
     uint32_t ngb = 0, cand = 0;
-    int top = 1, nr = 0;
-    uint32_t tot = 0;
-    if (lane == 0) S.stk[0] = 0;
+    int top = 1, nr = 0, nst = 0;
+    uint32_t avail = 1, tot = 0;
+    if (lane == 0) {
+        S.sfirst[0] = 0;
+        S.scnt[0] = 1;
+    }
     __syncthreads();
 
-    auto eval_tile = [&](int cnt) {
+    // pair tests and accepted-pair forces for the top `cnt` staged candidates
+    auto eval_top = [&](int cnt) {
+        const int base = nst - cnt;
         uint64_t mask = 0;
         for (int s = 0; s < cnt; s++) {
-            double dx = S.tx[s] - xi, dy = S.ty[s] - yi, dz = S.tz[s] - zi;
+            double dx = S.tx[base + s] - xi, dy = S.ty[base + s] - yi, dz = S.tz[base + s] - zi;
             double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            bool in = (r2 < R2sq) && (S.ti[s] != myidx);
+            bool in = (r2 < R2sq) & (S.ti[base + s] != mi);
             mask |= (uint64_t)in << s;
         }
         if (!G.act) mask = 0;
         ngb += __popcll(mask);
-        float hx = 0.f, hy = 0.f, hz = 0.f;
         while (mask) {
-            int s = __ffsll((long long)mask) - 1;
+            int s = __ffsll((long long)mask) - 1 + base;
             mask &= mask - 1;
             double dx = S.tx[s] - xi, dy = S.ty[s] - yi, dz = S.tz[s] - zi;
             double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            float fx = (float)dx, fy = (float)dy, fz = (float)dz;
-            float u2 = (float)r2;
-            float ri = rsq(u2 + eps2);
-            float K = K_of(fsqrt(u2), R2f, invdR);
-            float f = S.tm[s] * K * (ri * ri * ri);
-            hx = fmaf(f, fx, hx);
-            hy = fmaf(f, fy, hy);
-            hz = fmaf(f, fz, hz);
+            double ri = rsqrt64(r2 + eps2d);
+            double r = r2 > 1e-30 ? r2 * rsqrt64(r2) : 0.0;   // K = 1 below R1 anyway
+            double K = K_of64(r, R2, invdR64);
+            double f = (double)S.tm[s] * K * (ri * ri * ri);
+            hx = fma(f, dx, hx);
+            hy = fma(f, dy, hy);
+            hz = fma(f, dz, hz);
         }
-        kahan(acc.a[0], acc.c[0], hx);
-        kahan(acc.a[1], acc.c[1], hy);
-        kahan(acc.a[2], acc.c[2], hz);
+        cand += (uint32_t)cnt;
+        nst -= cnt;
+        __syncthreads();
     };
-    auto fill_tile = [&](int want) {
-        uint32_t pi = take_particles(S.rfirst, S.rcnt, nr, want, S.scan);
+    // move up to 64 candidate particles from the leaf ranges into the stage,
+    // keeping those within R2 (plus slack) of the group box
+    auto stage = [&](int want) {
+        uint32_t pi = take_items(S.rfirst, S.rcnt, nr, want, S.scan);
+        bool keep = false;
+        double4 q = make_double4(0, 0, 0, 0);
         if (lane < want) {
-            S.tx[lane] = A.x[pi];
-            S.ty[lane] = A.x[n + pi];
-            S.tz[lane] = A.x[2 * n + pi];
-            S.tm[lane] = (float)A.src[pi].w;
-            S.ti[lane] = pi;
+            q = A.src[pi];
+            double D = dist2(gap_pt(G.lo[0], G.hi[0], q.x), gap_pt(G.lo[1], G.hi[1], q.y),
+                             gap_pt(G.lo[2], G.hi[2], q.z));
+            keep = D < pad2;
         }
+        uint64_t m = __ballot(keep);
+        if (keep) {
+            int o = nst + __popcll(m & lt);
+            S.tx[o] = A.x[pi];
+            S.ty[o] = A.x[n + pi];
+            S.tz[o] = A.x[2 * n + pi];
+            S.tm[o] = (float)q.w;
+            S.ti[o] = pi;
+        }
+        nst += __popcll(m);
+        tot -= (uint32_t)want;
         __syncthreads();
     };
 
-    while (top > 0) {
-        int p = top < 64 ? top : 64;
-        int pmax = (kStk - kStkReserve - top) / 7;
-        if (p > pmax) p = pmax > 1 ? pmax : 1;
-        const bool have = lane < p;
-        uint32_t id = have ? S.stk[top - p + lane] : 0u;
-        top -= p;
-        __syncthreads();
+    while (avail > 0) {
+        const int want = step_width(top, avail);
+        uint32_t id = take_items(S.sfirst, S.scnt, top, want, S.scan);
+        avail -= (uint32_t)want;
+        const bool have = lane < want;
         bool leaf = false, opn = false;
         uint32_t first = 0, count = 0, child = 0, nch = 0;
         if (have) {
@@ -491,32 +555,29 @@ __global__ __launch_bounds__(64) void k_hard(ForceArgs A) {
         }
         nr += __popcll(m);
         tot += wave_sum(leaf ? count : 0u);
-        uint32_t k = opn ? nch : 0u;
-        uint32_t inc = wave_incl_scan(k);
+        m = __ballot(opn);
         if (opn) {
-            uint32_t b = (uint32_t)top + inc - k;
-            for (uint32_t j = 0; j < k; j++) S.stk[b + j] = child + j;
+            int o = top + __popcll(m & lt);
+            S.sfirst[o] = child;
+            S.scnt[o] = nch;
         }
-        top += (int)__shfl(inc, 63);
+        top += __popcll(m);
+        avail += wave_sum(opn ? nch : 0u);
+        HT_CHECK(top <= kStk && nr < kRQ && nst < kStage);
         __syncthreads();
         while (tot >= 64) {
-            fill_tile(64);
-            eval_tile(64);
-            cand += 64;
-            __syncthreads();
-            tot -= 64;
+            stage(64);
+            if (nst >= 64) eval_top(64);
         }
     }
-    if (tot > 0) {
-        fill_tile((int)tot);
-        eval_tile((int)tot);
-        cand += tot;
-    }
+    if (tot > 0) stage((int)tot);
+    while (nst > 0) eval_top(nst < 64 ? nst : 64);
+
     if (G.act) {
         const int64_t i = G.b0 + lane;
-        A.acc[i] = A.G * (acc.a[0] - acc.c[0]);
-        A.acc[n + i] = A.G * (acc.a[1] - acc.c[1]);
-        A.acc[2 * n + i] = A.G * (acc.a[2] - acc.c[2]);
+        A.acc[i] = (float)(A.Gd * hx);
+        A.acc[n + i] = (float)(A.Gd * hy);
+        A.acc[2 * n + i] = (float)(A.Gd * hz);
         if (A.ngb) A.ngb[i] = (int32_t)ngb;
     }
     uint32_t ngb_sum = wave_sum(G.act ? ngb : 0u);
@@ -526,8 +587,18 @@ __global__ __launch_bounds__(64) void k_hard(ForceArgs A) {
     }
 }
 
-void launch_hard(const ForceArgs &A, hipStream_t s) {
-    hipLaunchKernelGGL(k_hard, dim3((unsigned)A.n_groups), dim3(64), 0, s, A);
+__global__ __launch_bounds__(64) void k_hard(ForceArgs A) {
+    __shared__ HardLDS S;
+    const uint32_t ng = *A.ng;
+    for (uint32_t k = 0;; k++) {
+        const uint32_t grp = static_group(k, ng);
+        if (grp >= ng) break;
+        hard_group(A, S, grp);
+    }
+}
+
+void launch_hard(const ForceArgs &A, int n_wg, hipStream_t s) {
+    hipLaunchKernelGGL(k_hard, dim3((unsigned)n_wg), dim3(64), 0, s, A);
 }
 
 }  // namespace htree

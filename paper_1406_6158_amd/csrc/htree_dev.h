@@ -5,6 +5,21 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Invariant checks compiled only into host-emulation builds of the kernels.
+#ifdef HTREE_EMU_CHECKS
+#include <cstdio>
+#include <cstdlib>
+#define HT_CHECK(c)                                                                    \
+    do {                                                                               \
+        if (!(c)) {                                                                    \
+            fprintf(stderr, "HT_CHECK failed %s:%d: %s\n", __FILE__, __LINE__, #c);  \
+            abort();                                                                   \
+        }                                                                              \
+    } while (0)
+#else
+#define HT_CHECK(c) ((void)0)
+#endif
+
 namespace htree {
 
 constexpr int kMaxLevel = 21;          // 63-bit keys: 21 levels of 3 bits
@@ -122,6 +137,9 @@ struct BuildBufs {
     double *S;             // [3][nnmax] first mass moments
     uint32_t *arrive;      // [nnmax] bottom-up arrival counters
     int64_t nnmax;
+    // sink groups
+    uint32_t *gstart;      // [n+1] group start positions (ng + 1 used)
+    uint32_t *ng;          // device group count
 };
 
 // Host launch wrappers (build.hip).
@@ -129,6 +147,7 @@ void launch_bbox_keys(const BuildBufs &B, hipStream_t s);
 void launch_sort(BuildBufs &B, hipStream_t s);
 void launch_gather(BuildBufs &B, hipStream_t s);
 void launch_topology(BuildBufs &B, bool moments, hipStream_t s);
+void launch_groups(BuildBufs &B, int g, hipStream_t s);
 void launch_check_finite(const BuildBufs &B, hipStream_t s);
 void launch_radix_u32(uint32_t *key_in, uint32_t *val_in, uint32_t *key_out, uint32_t *val_out,
                       uint32_t *hist, const uint32_t *count_dev, int64_t nmax, int shift,
@@ -139,24 +158,26 @@ void launch_scan_u32(uint32_t *data, int64_t n, uint32_t *part, uint32_t *total,
 // Force kernels (force.hip).
 struct ForceArgs {
     const Node *node;
+    const uint32_t *gstart;   // group k is sorted positions [gstart[k], gstart[k+1])
+    const uint32_t *ng;       // device group count
     const double4 *src;       // sorted build-frame positions and masses
     const double *x;          // [3][n] sorted FP64 positions (hard test)
     const Frame *frame;
     int64_t n;
     int32_t g;                // group size (64)
-    int64_t n_groups;
     float G, eps2;
     float R2f, invdR;         // changeover: Y = (R2 - r) * invdR
     double R2sq;              // exact contract radius squared
+    double Gd, eps2d, R2d, invdR64;   // FP64 copies for the hard force
     float *acc;               // [3][n] sorted order output
     float *pot;               // [n] or null
     int32_t *ngb;             // [n] or null
-    uint32_t *gcount;         // [3][n_groups] list sizes or null
+    uint32_t *gcount;         // [3][n] list sizes per group (first ng used) or null
     unsigned long long *tally;  // [4] interaction tallies
     uint32_t *status;
 };
-void launch_soft(const ForceArgs &A, bool hybrid, bool pot, hipStream_t s);
-void launch_hard(const ForceArgs &A, hipStream_t s);
+void launch_soft(const ForceArgs &A, bool hybrid, bool pot, int n_wg, hipStream_t s);
+void launch_hard(const ForceArgs &A, int n_wg, hipStream_t s);
 
 // Integrator and layout kernels (integrate.hip).
 void launch_kick_drift(double *x, float *v, const float *a1, float c1, const float *a2, float c2,

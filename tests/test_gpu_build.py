@@ -58,6 +58,7 @@ def test_build_bit_exact(orc, case, n_crit):
         assert np.array_equal(g[f][gk].astype(np.int64), o[f][ok].astype(np.int64)), f
     assert np.array_equal(g["M"][gk], o["M"][ok])
     assert np.array_equal(g["com"][:, gk], o["com"][:, ok])
+    assert np.array_equal(t.group_starts().astype(np.int64), T.group_starts())
 
 
 def test_build_deterministic():

@@ -1,0 +1,69 @@
+"""Parity at the benchmark's full sizes, in the launch configuration the
+benchmark times: N = 2^20 Plummer (eps 0.01, theta 0.5, ~64 neighbours) and
+N = 2^23 Hernquist (eps 0.005).  Trees and list sizes are compared in full;
+forces on sampled groups / sinks the oracle evaluates one by one."""
+import numpy as np
+import pytest
+
+import synth
+from tests._gpu import as_inputs, make_tree, need_gpu, rel_err, report
+
+pytestmark = pytest.mark.gpu
+
+
+def _check(orc, torch, P, wl, theta, n_groups_sample, n_sink_sample, full_counts):
+    x, v, m = wl.make()
+    x, v32, m32, v64, m64 = as_inputs(x, v, m)
+    n = x.shape[1]
+    print(wl.name, "theta", theta, "n", n, flush=True)
+    t = make_tree(P, torch, x, v32, m32, eps=wl.eps, theta=theta, R1=wl.R1, R2=wl.R2,
+                  n_crit=wl.n_crit)
+    t.build_tree()
+    a_s = t.soft_force()
+    a_h, ngb = t.hard_force()
+    t.sync()
+    keys, perm, lo, side = t.export_keys()
+    T = orc.Tree(x, m64, n_crit=wl.n_crit, theta=theta)
+    operm, okey, _ = T.sorted()
+    assert np.array_equal(keys, okey) and np.array_equal(perm.astype(np.int64), operm)
+    g = t.export_nodes()
+    o = T.nodes()
+    gk = np.lexsort((g["first"], g["level"]))
+    ok = np.lexsort((o["first"], o["level"]))
+    assert len(gk) == len(ok)
+    for f in ("level", "first", "count"):
+        assert np.array_equal(g[f][gk].astype(np.int64), o[f][ok].astype(np.int64))
+    assert np.array_equal(g["com"][:, gk], o["com"][:, ok])
+    gst = T.group_starts()
+    assert np.array_equal(t.group_starts().astype(np.int64), gst)
+    npc, nfar, nnear = t.group_counts()
+    ng = npc.size
+    groups = synth.sample_indices(ng, n_groups_sample, wl.sample_seed)
+    if full_counts:
+        opc, ofar, onear = T.walk_counts(wl.R2, 1)
+        assert np.array_equal(npc, opc) and np.array_equal(nfar, ofar)
+        assert np.array_equal(nnear, onear)
+    oacc, _, _ = T.soft(1.0, wl.eps, wl.R1, wl.R2, 1, groups=groups)
+    sinks = np.concatenate([operm[gst[k]:gst[k + 1]] for k in groups])
+    e = rel_err(a_s.cpu().numpy()[:, sinks].astype(np.float64), oacc[:, sinks])
+    report("soft sampled groups", e)
+    assert np.percentile(e, 99) <= 1e-5
+    hs = synth.sample_indices(n, n_sink_sample, wl.sample_seed + 1)
+    oah, _, ongb = orc.split_direct(x, m64, 1.0, wl.eps, wl.R1, wl.R2, sinks=hs, soft=False)
+    assert np.array_equal(ngb.cpu().numpy()[hs].astype(np.int64), ongb)
+    e = rel_err(a_h.cpu().numpy()[:, hs].astype(np.float64), oah)
+    report("hard sampled sinks", e[ongb > 0])
+    assert np.percentile(e[ongb > 0], 99) <= 1e-5
+    print("mean ngb %.1f, mean list entries per group %.0f" %
+          (ongb.mean(), (npc + nfar + nnear).mean()), flush=True)
+
+
+def test_plummer_2e20(orc):
+    torch, P = need_gpu()
+    _check(orc, torch, P, synth.WORKLOADS["plummer1m"], 0.5, 96, 2048, True)
+
+
+@pytest.mark.parametrize("theta", [0.4, 0.8])
+def test_hernquist_2e23(orc, theta):
+    torch, P = need_gpu()
+    _check(orc, torch, P, synth.WORKLOADS["hernquist8m"], theta, 32, 512, False)

@@ -1,0 +1,99 @@
+"""GPU two-timestep leapfrog vs the oracle's nested kick-drift-kick."""
+import numpy as np
+import pytest
+
+import synth
+from tests._gpu import as_inputs, make_tree, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def _run_gpu(P, torch, x, v32, m32, steps, **kw):
+    t = make_tree(P, torch, x, v32, m32, **kw)
+    t.step(steps)
+    t.sync()
+    xg, vg = t.get_state()
+    return xg.cpu().numpy(), vg.cpu().numpy().astype(np.float64)
+
+
+@pytest.mark.parametrize("n_sub,dt,steps", [(1, 1.0 / 128, 10), (2, 2.0 / 128, 5), (4, 4.0 / 128, 3)])
+def test_step_matches_oracle(orc, n_sub, dt, steps):
+    torch, P = need_gpu()
+    wl = synth.WORKLOADS["plummer4k"]
+    x, v, m = wl.make()
+    x, v32, m32, v64, m64 = as_inputs(x, v, m)
+    print("step n_sub", n_sub, "dt", dt, "steps", steps, flush=True)
+    xg, vg = _run_gpu(P, torch, x, v32, m32, steps, eps=wl.eps, theta=wl.theta, R1=wl.R1,
+                      R2=wl.R2, dt_soft=dt, n_sub=n_sub)
+    xo, vo = orc.step(x, v64, m64, 1.0, wl.eps, wl.theta, wl.R1, wl.R2, 16, 64, 1, dt, n_sub,
+                      steps)
+    dx = np.abs(xg - xo).max()
+    dv = np.abs(vg - vo).max()
+    print("max |dx| %.3e  max |dv| %.3e" % (dx, dv), flush=True)
+    assert dx < 1e-5 and dv < 1e-3
+    assert np.percentile(np.abs(vg - vo), 99) < 1e-6
+
+
+def test_plain_mode_matches_oracle(orc):
+    torch, P = need_gpu()
+    wl = synth.WORKLOADS["plummer4k"]
+    x, v, m = wl.make()
+    x, v32, m32, v64, m64 = as_inputs(x, v, m)
+    xg, vg = _run_gpu(P, torch, x, v32, m32, 10, eps=wl.eps, theta=wl.theta, hybrid=0,
+                      dt_soft=1.0 / 128, n_sub=1)
+    xo, vo = orc.step(x, v64, m64, 1.0, wl.eps, wl.theta, 0.0, 0.0, 16, 64, 0, 1.0 / 128, 1, 10)
+    assert np.abs(xg - xo).max() < 1e-5 and np.abs(vg - vo).max() < 1e-3
+
+
+def test_single_substep_hybrid_equals_plain_at_theta0():
+    # theta = 0 makes soft + hard the direct force, as is the plain tree force
+    torch, P = need_gpu()
+    wl = synth.WORKLOADS["plummer4k"]
+    x, v, m = wl.make()
+    x, v32, m32, _, _ = as_inputs(x, v, m)
+    kw = dict(eps=wl.eps, theta=0.0, dt_soft=1.0 / 128, n_sub=1)
+    xh, vh = _run_gpu(P, torch, x, v32, m32, 5, R1=wl.R1, R2=wl.R2, hybrid=1, **kw)
+    xp, vp = _run_gpu(P, torch, x, v32, m32, 5, hybrid=0, **kw)
+    assert np.abs(xh - xp).max() < 1e-6 and np.abs(vh - vp).max() < 1e-4
+
+
+def test_step_deterministic():
+    torch, P = need_gpu()
+    x, v, m = synth.plummer(20000, 61)
+    x, v32, m32, _, _ = as_inputs(x, v, m)
+    R2 = synth.r2_for_neighbours("plummer", 20000, 64)
+    a = _run_gpu(P, torch, x, v32, m32, 2, R1=R2 / 2, R2=R2, dt_soft=1.0 / 32)
+    b = _run_gpu(P, torch, x, v32, m32, 2, R1=R2 / 2, R2=R2, dt_soft=1.0 / 32)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_kick_drift_with_given_acceleration():
+    torch, P = need_gpu()
+    x, v, m = synth.plummer(3000, 62)
+    x, v32, m32, _, _ = as_inputs(x, v, m)
+    t = make_tree(P, torch, x, v32, m32)
+    acc = np.random.default_rng(1).normal(size=(3, 3000)).astype(np.float32)
+    t.kick_drift(0.25, torch.from_numpy(acc).cuda(), 0.125)
+    t.sync()
+    xg, vg = t.get_state()
+    vref = v32 + np.float32(0.25) * acc
+    np.testing.assert_array_equal(vg.cpu().numpy(), vref)
+    np.testing.assert_allclose(xg.cpu().numpy(), x + 0.125 * vref.astype(np.float64),
+                               rtol=0, atol=1e-15)
+
+
+def test_energy_error_reported(orc):
+    """Energy drift over the small Plummer run, GPU vs oracle (the paper
+    prints no energy error to pin against: parity unpinned, reported)."""
+    torch, P = need_gpu()
+    wl = synth.WORKLOADS["plummer4k"]
+    x, v, m = wl.make()
+    x, v32, m32, v64, m64 = as_inputs(x, v, m)
+    e0 = sum(orc.energy(x, v64, m64, 1.0, wl.eps))
+    xg, vg = _run_gpu(P, torch, x, v32, m32, 5, eps=wl.eps, theta=wl.theta, R1=wl.R1,
+                      R2=wl.R2, dt_soft=2.0 / 128, n_sub=2)
+    eg = sum(orc.energy(xg, vg, m64, 1.0, wl.eps))
+    xo, vo = orc.step(x, v64, m64, 1.0, wl.eps, wl.theta, wl.R1, wl.R2, 16, 64, 1, 2.0 / 128, 2, 5)
+    eo = sum(orc.energy(xo, vo, m64, 1.0, wl.eps))
+    print("relative energy error: gpu %.3e oracle %.3e" % ((eg - e0) / abs(e0), (eo - e0) / abs(e0)))
+    assert abs(eg - eo) / abs(e0) < 1e-6

@@ -141,12 +141,13 @@ def test_moments_and_geometry(orc):
                                rtol=1e-12, atol=1e-14 * m.sum())
 
 
-def _brute_lists(T, g, k, R2, hybrid):
+def _brute_lists(T, k, R2, hybrid):
     """Accept/near sets derived node by node: a cell is on the list iff it is
     accepted (or a leaf) while every proper ancestor was opened."""
     nd = T.nodes()
     perm, key, u = T.sorted()
-    b, e = k * g, min((k + 1) * g, T.n)
+    st = T.group_starts()
+    b, e = st[k], st[k + 1]
     glo, ghi = u[:, b:e].min(axis=1), u[:, b:e].max(axis=1)
 
     def dist2(lo, hi):
@@ -181,10 +182,10 @@ def _brute_lists(T, g, k, R2, hybrid):
 @pytest.mark.parametrize("hybrid", [0, 1])
 def test_walk_vs_bruteforce(orc, hybrid):
     x, v, m = synth.plummer(512, 21)
-    T = orc.Tree(x, m, n_crit=8, theta=0.6)
-    for k in range(0, 512 // 32):
-        pc, far, near = T.walk_group(32, k, 0.25, hybrid)
-        ref = _brute_lists(T, 32, k, 0.25, hybrid)
+    T = orc.Tree(x, m, n_crit=8, theta=0.6, group=32)
+    for k in range(T.ngroups):
+        pc, far, near = T.walk_group(k, 0.25, hybrid)
+        ref = _brute_lists(T, k, 0.25, hybrid)
         assert set(pc.tolist()) == ref["pc"]
         assert set(far.tolist()) == ref["far"]
         assert set(near.tolist()) == ref["near"]
@@ -195,13 +196,13 @@ def test_walk_coverage(orc, hybrid):
     x, v, m = synth.plummer(8192, 22)
     T = orc.Tree(x, m, n_crit=16, theta=0.5)
     nd = T.nodes()
-    for k in range(0, 8192 // 64, 5):
-        pc, far, near = T.walk_group(64, k, 0.2, hybrid)
+    for k in range(0, T.ngroups, 5):
+        pc, far, near = T.walk_group(k, 0.2, hybrid)
         tot = nd["count"][pc].sum() + nd["count"][far].sum() + nd["count"][near].sum()
         assert tot == 8192
         assert nd["M"][pc].sum() + nd["M"][far].sum() + nd["M"][near].sum() == \
             pytest.approx(m.sum(), rel=1e-13)
-    npc, nfar, nnear = T.walk_counts(64, 0.2, hybrid)
+    npc, nfar, nnear = T.walk_counts(0.2, hybrid)
     if not hybrid:
         assert np.all(nnear == 0)
 
@@ -211,7 +212,7 @@ def test_list_length_decreases_with_theta(orc):
     tot = []
     for th in (0.3, 0.5, 0.8):
         T = orc.Tree(x, m, n_crit=16, theta=th)
-        c = T.walk_counts(64, 0.1, 1)
+        c = T.walk_counts(0.1, 1)
         tot.append(c[0] + c[1] + c[2])
     assert np.all(tot[1] <= tot[0]) and np.all(tot[2] <= tot[1])
 
@@ -221,7 +222,7 @@ def test_theta_zero_equals_direct(orc, hybrid):
     x, v, m = synth.plummer(4096, 1)
     wl = synth.WORKLOADS["plummer4k"]
     T = orc.Tree(x, m, n_crit=16, theta=0.0)
-    acc, pot, inter = T.soft(64, 1.0, wl.eps, wl.R1, wl.R2, hybrid, potential=True)
+    acc, pot, inter = T.soft(1.0, wl.eps, wl.R1, wl.R2, hybrid, potential=True)
     assert inter == 4096 * 4096
     if hybrid:
         _, ref, _ = orc.split_direct(x, m, 1.0, wl.eps, wl.R1, wl.R2)
@@ -242,7 +243,68 @@ def test_tree_force_error_reported(orc):
     ah, _, _ = orc.split_direct(x, m, 1.0, wl.eps, wl.R1, wl.R2, soft=False)
     for hybrid in (0, 1):
         T = orc.Tree(x, m, n_crit=16, theta=0.5)
-        acc, _, _ = T.soft(64, 1.0, wl.eps, wl.R1, wl.R2, hybrid)
+        acc, _, _ = T.soft(1.0, wl.eps, wl.R1, wl.R2, hybrid)
         tot = acc + (ah if hybrid else 0.0)
         e = np.linalg.norm(tot - ref, axis=0) / np.linalg.norm(ref, axis=0)
         assert np.percentile(e, 99) < 1e-2
+
+
+@pytest.mark.parametrize("n,g,n_crit,seed", [(1, 64, 16, 1), (64, 64, 16, 2), (65, 64, 16, 3),
+                                             (20000, 64, 16, 4), (5000, 32, 8, 5),
+                                             (3000, 16, 64, 6)])
+def test_sink_groups(orc, n, g, n_crit, seed):
+    """Groups partition the sorted particles, hold at most g each, and each is a
+    whole cell, a run of consecutive sibling cells of one parent, or a g-chunk
+    of an oversized leaf; consecutive sibling runs could not have been merged."""
+    x, v, m = synth.plummer(n, seed)
+    if n > 1000:
+        x[:, 500:700] = x[:, 499:500]          # oversized deepest-level leaf
+    T = orc.Tree(x, m, n_crit=n_crit, group=g)
+    st = T.group_starts()
+    assert st[0] == 0 and st[-1] == n and np.all(np.diff(st) > 0)
+    cnt = np.diff(st)
+    assert np.all(cnt <= g)
+    nd = T.nodes()
+    first, count, parent = nd["first"], nd["count"], nd["parent"]
+    end = first + count
+    kinds = []
+    for b, e in zip(st[:-1], st[1:]):
+        # smallest node containing [b, e)
+        inside = np.nonzero((first <= b) & (end >= e))[0]
+        c = inside[np.argmax(nd["level"][inside])]
+        if first[c] == b and end[c] == e:
+            assert count[c] <= g or nd["nchild"][c] == 0
+            kinds.append(("cell", c))
+            continue
+        if nd["nchild"][c] == 0:                    # chunk of an oversized leaf
+            assert count[c] > g and (b - first[c]) % g == 0
+            kinds.append(("chunk", c))
+            continue
+        ch = np.nonzero(parent == c)[0]
+        sel = ch[(first[ch] >= b) & (end[ch] <= e)]
+        assert first[sel].min() == b and end[sel].max() == e       # whole children
+        assert np.all(count[sel] <= g) and count[sel].sum() == e - b
+        assert count[c] > g
+        kinds.append(("run", c, sel))
+    # packing is greedy: a run followed by a run of the same parent could not
+    # have absorbed that run's first child
+    for k in range(len(kinds) - 1):
+        a, b2 = kinds[k], kinds[k + 1]
+        if a[0] == "run" and b2[0] == "run" and a[1] == b2[1]:
+            nxt = b2[2][np.argmin(first[b2[2]])]
+            if first[nxt] == st[k + 1]:
+                assert cnt[k] + count[nxt] > g
+
+
+def test_groups_are_compact(orc):
+    x, v, m = synth.plummer(1 << 16, 7)
+    T = orc.Tree(x, m, n_crit=16, group=64)
+    st = T.group_starts()
+    perm, key, u = T.sorted()
+    nd = T.nodes()
+    # every group lies inside one cell whose side bounds its bounding box
+    for b, e in zip(st[:-1:37], st[1::37]):
+        inside = np.nonzero((nd["first"] <= b) & (nd["first"] + nd["count"] >= e))[0]
+        c = inside[np.argmax(nd["level"][inside])]
+        ext = (u[:, b:e].max(axis=1) - u[:, b:e].min(axis=1)).max()
+        assert ext <= nd["l"][c]
