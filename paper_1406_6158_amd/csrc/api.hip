@@ -138,7 +138,7 @@ void carve(Carver &C, htree_ctx *c) {
     B.pre_count = C.take<uint32_t>(nnmax);
     B.node = C.take<Node>(nnmax);
     B.S = C.take<double>(3 * nnmax);
-    B.arrive = C.take<uint32_t>(nnmax);
+    B.lstart = C.take<uint32_t>(kMaxLevel + 2);
     B.gstart = C.take<uint32_t>(n + 1);
     B.ng = C.take<uint32_t>(4);
     c->tmp3 = C.take<float>(3 * n);

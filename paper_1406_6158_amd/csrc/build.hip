@@ -150,14 +150,35 @@ __global__ __launch_bounds__(kBoxNT) void k_bbox(const double *x, int64_t n, dou
     }
 }
 
-__global__ void k_frame(const double *part, int nb, Frame *F, double R2) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(kBoxNT) void k_frame(const double *part, int nb, Frame *F,
+                                                  double R2) {
+    __shared__ double sh[kBoxNT / 64][6];
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int b = 0; b < nb; b++)
+    for (int b = threadIdx.x; b < nb; b += kBoxNT)
         for (int a = 0; a < 3; a++) {
             lo[a] = fmin(lo[a], part[b * 6 + a]);
             hi[a] = fmax(hi[a], part[b * 6 + 3 + a]);
         }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int a = 0; a < 3; a++) {
+        lo[a] = wave_min(lo[a]);
+        hi[a] = wave_max(hi[a]);
+    }
+    if (lane == 0)
+        for (int a = 0; a < 3; a++) { sh[w][a] = lo[a]; sh[w][3 + a] = hi[a]; }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int k = 1; k < kBoxNT / 64; k++)
+        for (int a = 0; a < 3; a++) {
+            lo[a] = fmin(sh[0][a], sh[k][a]);
+            hi[a] = fmax(sh[0][3 + a], sh[k][3 + a]);
+            sh[0][a] = lo[a];
+            sh[0][3 + a] = hi[a];
+        }
+    for (int a = 0; a < 3; a++) {
+        lo[a] = sh[0][a];
+        hi[a] = sh[0][3 + a];
+    }
     // extent of the build frame u = x - lo: rounding is monotone, so the
     // largest rounded difference is the rounded difference of the extremes
     double ext = 0.0;
@@ -224,7 +245,7 @@ void launch_bbox_keys(const BuildBufs &B, hipStream_t s) {
     if (nb < 1) nb = 1;
     const double *x = B.x[B.cur];
     hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(kBoxNT), 0, s, x, n, B.bbox_part, B.status);
-    hipLaunchKernelGGL(k_frame, dim3(1), dim3(64), 0, s, B.bbox_part, nb, B.frame, B.R2);
+    hipLaunchKernelGGL(k_frame, dim3(1), dim3(kBoxNT), 0, s, B.bbox_part, nb, B.frame, B.R2);
     hipLaunchKernelGGL(k_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n,
                        B.frame, B.key[0], B.idx[0]);
 }
@@ -447,8 +468,7 @@ __global__ __launch_bounds__(256) void k_pre2bfs(const uint32_t *bfs2pre, const 
 __global__ __launch_bounds__(256) void k_fill_nodes(
     const uint64_t *key, const int8_t *leaflev, const uint32_t *nstart, const uint32_t *bfs2pre,
     const uint32_t *pre2bfs, const uint32_t *lvl, const uint32_t *pre_first,
-    const uint32_t *pre_count, const uint32_t *nn, const Frame *F, double invth2, Node *node,
-    uint32_t *arrive) {
+    const uint32_t *pre_count, const uint32_t *nn, const Frame *F, double invth2, Node *node) {
     uint32_t b = blockIdx.x * 256 + threadIdx.x;
     if (b >= *nn) return;
     uint32_t p = bfs2pre[b];
@@ -481,53 +501,53 @@ __global__ __launch_bounds__(256) void k_fill_nodes(
         uint32_t q = compact3(k0 >> (2 - a));
         N.blo[a] = (double)(q >> (kMaxLevel - lev)) * l;
     }
-    arrive[b] = 0;
 }
 
-// Bottom-up moments: each leaf sums its particles in sorted order, then the
-// last child to arrive at a parent sums the children in octant order.
-__global__ __launch_bounds__(256) void k_moments(Node *node, const double4 *src, double *S,
-                                                 const uint32_t *nn_dev, int64_t nnmax,
-                                                 uint32_t *arrive) {
+// Start of each level in the level-ordered node array (levels are contiguous
+// and every level from 0 to the deepest one is present); entries past the
+// deepest level are set to the node count.  Each entry has a single writer:
+// the first node of its level, or the last node for the levels beyond.
+__global__ __launch_bounds__(256) void k_level_starts(const uint32_t *lvl, const uint32_t *nn_dev,
+                                                      uint32_t *lstart) {
     uint32_t b = blockIdx.x * 256 + threadIdx.x;
     uint32_t nn = *nn_dev;
     if (b >= nn) return;
-    uint32_t meta = node[b].meta;
-    if ((meta & 255u) != 0) return;   // internal: done by the last child
-    double M = 0.0, s[3] = {0.0, 0.0, 0.0};
-    uint32_t f = node[b].first, c = node[b].count;
-    for (uint32_t i = f; i < f + c; i++) {
-        double4 q = src[i];
-        M += q.w;
-        s[0] = fma(q.w, q.x, s[0]);
-        s[1] = fma(q.w, q.y, s[1]);
-        s[2] = fma(q.w, q.z, s[2]);
-    }
-    uint32_t cur = b;
-    for (;;) {
-        Node &N = node[cur];
+    if (b == 0 || lvl[b] != lvl[b - 1]) lstart[lvl[b]] = b;
+    if (b == nn - 1)
+        for (uint32_t l = lvl[b] + 1; l <= (uint32_t)kMaxLevel + 1; l++) lstart[l] = nn;
+}
+
+// Moments of the nodes of one level, deepest level first: a leaf sums its
+// particles in sorted order (M += m, S = fma(m, u, S)); an internal node sums
+// its children's M and S in octant order; COM = S / M.
+__global__ __launch_bounds__(256) void k_moments_level(Node *node, const double4 *src, double *S,
+                                                       const uint32_t *lstart, int level,
+                                                       int64_t nnmax) {
+    const uint32_t b0 = lstart[level], b1 = lstart[level + 1];
+    for (uint32_t b = b0 + blockIdx.x * 256 + threadIdx.x; b < b1; b += gridDim.x * 256) {
+        Node &N = node[b];
+        uint32_t nch = N.meta & 255u;
+        double M = 0.0, s[3] = {0.0, 0.0, 0.0};
+        if (nch == 0) {
+            for (uint32_t i = N.first; i < N.first + N.count; i++) {
+                double4 q = src[i];
+                M += q.w;
+                s[0] = fma(q.w, q.x, s[0]);
+                s[1] = fma(q.w, q.y, s[1]);
+                s[2] = fma(q.w, q.z, s[2]);
+            }
+        } else {
+            for (uint32_t k = 0; k < nch; k++) {
+                uint32_t c = N.child + k;
+                M += node[c].M;
+                for (int a = 0; a < 3; a++) s[a] += S[a * nnmax + c];
+            }
+        }
         N.M = M;
         for (int a = 0; a < 3; a++) {
-            S[a * nnmax + cur] = s[a];
+            S[a * nnmax + b] = s[a];
             N.com[a] = (M != 0.0) ? s[a] / M : N.blo[a] + 0.5 * N.l;
         }
-        if (cur == 0) return;
-        uint32_t par = N.parent;
-        __threadfence();
-        uint32_t nchp = node[par].meta & 255u;
-        uint32_t old = atomicAdd(&arrive[par], 1u);
-        if (old != nchp - 1) return;
-        __threadfence();
-        uint32_t c0 = node[par].child;
-        M = 0.0;
-        s[0] = s[1] = s[2] = 0.0;
-        for (uint32_t k = 0; k < nchp; k++) {
-            M += __hip_atomic_load(&node[c0 + k].M, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            for (int a = 0; a < 3; a++)
-                s[a] += __hip_atomic_load(&S[a * nnmax + c0 + k], __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-        }
-        cur = par;
     }
 }
 
@@ -547,10 +567,15 @@ void launch_topology(BuildBufs &B, bool moments, hipStream_t s) {
     hipLaunchKernelGGL(k_pre2bfs, dim3(gn), dim3(256), 0, s, B.bfs2pre, B.nn, B.pre2bfs);
     hipLaunchKernelGGL(k_fill_nodes, dim3(gn), dim3(256), 0, s, key, B.leaflev, B.nstart,
                        B.bfs2pre, B.pre2bfs, B.lvl_key2, B.pre_first, B.pre_count, B.nn, B.frame,
-                       B.invth2, B.node, B.arrive);
-    if (moments)
-        hipLaunchKernelGGL(k_moments, dim3(gn), dim3(256), 0, s, B.node, B.src, B.S, B.nn,
-                           B.nnmax, B.arrive);
+                       B.invth2, B.node);
+    if (moments) {
+        hipLaunchKernelGGL(k_level_starts, dim3(gn), dim3(256), 0, s, B.lvl_key2, B.nn, B.lstart);
+        // one grid-stride launch per level, deepest first
+        unsigned gl = gn < 1024u ? gn : 1024u;
+        for (int l = kMaxLevel; l >= 0; l--)
+            hipLaunchKernelGGL(k_moments_level, dim3(gl), dim3(256), 0, s, B.node, B.src, B.S,
+                               B.lstart, l, B.nnmax);
+    }
 }
 
 }  // namespace htree

@@ -135,7 +135,7 @@ struct BuildBufs {
     uint32_t *pre_count;   // [nnmax]
     Node *node;            // [nnmax] level order
     double *S;             // [3][nnmax] first mass moments
-    uint32_t *arrive;      // [nnmax] bottom-up arrival counters
+    uint32_t *lstart;      // [kMaxLevel + 2] first node of each level
     int64_t nnmax;
     // sink groups
     uint32_t *gstart;      // [n+1] group start positions (ng + 1 used)
