@@ -63,7 +63,8 @@ typedef struct {
     int32_t n_sub;        /* hard substeps per soft step, dt_h = dt_s / n_sub (>= 1) */
     int32_t hybrid;       /* 1: hard/soft split; 0: plain tree (normal-tree mode)    */
     int32_t n_crit;       /* a cell splits while it holds >= n_crit particles (>= 1) */
-    int32_t group_size;   /* sinks sharing one walk: 64 (one wavefront)              */
+    int32_t group_size;   /* at most this many sinks share one walk, 1..64 (64: one  */
+                          /* sink per lane of a wavefront)                          */
     int32_t precision;    /* 0: FP32 interactions with compensated tile sums         */
     int32_t flags;        /* HTREE_F_*                                               */
 } htree_params;
@@ -89,6 +90,19 @@ void htree_default_params(htree_params *p);
 /* Exact number of workspace bytes a context for n particles needs (0 if the
  * parameters are invalid).  This is the device footprint used for admission. */
 size_t htree_workspace_bytes(const htree_params *p, int64_t n);
+
+/* Batch of S independent systems in one context (one launch per phase serves
+ * all of them).  p[s] and n[s] describe system s (1 <= S <= 65536, total
+ * particles <= 2^27).  G, eps, theta, R1, R2 may differ between systems;
+ * dt_soft, n_sub, hybrid, n_crit, group_size, precision and flags must equal
+ * those of system 0.  Particle arrays passed to the other calls concatenate
+ * the systems in order: system s occupies positions [n_0 + ... + n_{s-1},
+ * ... + n_s) of every [3][N] or [N] array (N = total).  Systems never
+ * interact.  Same errors as htree_create; 0 bytes if invalid. */
+size_t htree_batch_workspace_bytes(const htree_params *p, const int64_t *n, int32_t S);
+htree_status htree_batch_create(htree_ctx **ctx, const htree_params *p, const int64_t *n,
+                                int32_t S, void *d_workspace, size_t ws_bytes, void *hip_stream);
+int32_t htree_system_count(htree_ctx *ctx);
 
 /* Creates a context for n >= 1 particles.  d_workspace must hold ws_bytes >=
  * htree_workspace_bytes(p, n) bytes, 256-byte aligned, and stay valid until
@@ -169,8 +183,9 @@ htree_status htree_group_counts(htree_ctx *ctx, int32_t *n_cells, int32_t *n_far
                                 int32_t *n_near);
 
 /* Copies the sorted keys, the permutation (sorted position -> caller index)
- * and the build frame (lo[3], side) of the last build to host memory (any
- * pointer may be NULL).  Synchronises the stream. */
+ * and the build frame of every system (lo[3], side: 4 doubles per system) of
+ * the last build to host memory (any pointer may be NULL).  Synchronises the
+ * stream. */
 htree_status htree_export_keys(htree_ctx *ctx, uint64_t *keys, int32_t *perm,
                                double *frame4);
 

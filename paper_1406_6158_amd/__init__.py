@@ -12,11 +12,12 @@ from __future__ import annotations
 import ctypes as C
 
 from ._abi import (F_POT, F_TIMING, HTREE_EINVAL, HTREE_ENOMEM, HTREE_EOVERFLOW, HTREE_ESTATE,
-                   HTreeError, Params, Counters, check, default_params, lib, workspace_bytes)
+                   HTreeError, Params, Counters, batch_arrays, batch_workspace_bytes, check,
+                   default_params, lib, workspace_bytes)
 
 __all__ = ["HTree", "Params", "Counters", "HTreeError", "default_params", "workspace_bytes",
-           "lib", "F_POT", "F_TIMING", "HTREE_EINVAL", "HTREE_ENOMEM", "HTREE_EOVERFLOW",
-           "HTREE_ESTATE"]
+           "batch_workspace_bytes", "lib", "F_POT", "F_TIMING", "HTREE_EINVAL", "HTREE_ENOMEM",
+           "HTREE_EOVERFLOW", "HTREE_ESTATE"]
 
 
 def _ptr(t):
@@ -24,30 +25,48 @@ def _ptr(t):
 
 
 class HTree:
-    """One particle system on one GPU.
+    """One particle system, or a batch of independent systems, on one GPU.
 
-    ``params`` is a ``Params`` (see ``default_params``); ``n`` the particle
-    count.  The workspace is a torch uint8 tensor on ``device``; calls are
+    ``params`` is a ``Params`` (see ``default_params``) and ``n`` the particle
+    count; for a batch, ``params`` is a list with one ``Params`` per system and
+    ``n`` the list of their sizes (arrays then concatenate the systems in
+    order).  The workspace is a torch uint8 tensor on ``device``; calls are
     enqueued on ``stream`` (default: torch's current stream at construction).
     """
 
-    def __init__(self, n: int, params: Params, device="cuda", stream=None):
+    def __init__(self, n, params, device="cuda", stream=None):
         import torch
         self.torch = torch
-        self.n = int(n)
+        self.batch = isinstance(n, (list, tuple))
+        self.sizes = [int(v) for v in n] if self.batch else [int(n)]
+        self.n = sum(self.sizes)
         self.params = params
         self.device = torch.device(device)
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream()
-            nbytes = workspace_bytes(params, self.n)
+            if self.batch:
+                pa, na = batch_arrays(params, self.sizes)
+                nbytes = int(lib().htree_batch_workspace_bytes(pa, na, len(self.sizes)))
+            else:
+                nbytes = workspace_bytes(params, self.n)
             if nbytes == 0:
                 raise HTreeError(HTREE_EINVAL, lib().htree_last_error().decode())
+            self.nbytes = nbytes
             self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
             h = C.c_void_p()
-            check(lib().htree_create(C.byref(h), C.byref(params), self.n,
-                                     C.c_void_p(self.workspace.data_ptr()), nbytes,
-                                     C.c_void_p(self.stream.cuda_stream)))
+            if self.batch:
+                check(lib().htree_batch_create(C.byref(h), pa, na, len(self.sizes),
+                                               C.c_void_p(self.workspace.data_ptr()), nbytes,
+                                               C.c_void_p(self.stream.cuda_stream)))
+            else:
+                check(lib().htree_create(C.byref(h), C.byref(params), self.n,
+                                         C.c_void_p(self.workspace.data_ptr()), nbytes,
+                                         C.c_void_p(self.stream.cuda_stream)))
         self._h = h
+
+    @property
+    def group_size(self):
+        return (self.params[0] if self.batch else self.params).group_size
 
     # -- lifetime ---------------------------------------------------------------
     def close(self):
@@ -161,9 +180,12 @@ class HTree:
         import numpy as np
         keys = np.zeros(self.n, np.uint64)
         perm = np.zeros(self.n, np.int32)
-        fr = np.zeros(4)
+        fr = np.zeros(4 * len(self.sizes))
         check(lib().htree_export_keys(self._h, C.c_void_p(keys.ctypes.data),
                                       C.c_void_p(perm.ctypes.data), C.c_void_p(fr.ctypes.data)))
+        if self.batch:
+            fr = fr.reshape(-1, 4)
+            return keys, perm, fr[:, :3].copy(), fr[:, 3].copy()
         return keys, perm, fr[:3].copy(), float(fr[3])
 
     def export_nodes(self):

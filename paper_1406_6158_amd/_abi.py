@@ -69,6 +69,11 @@ def lib() -> C.CDLL:
     L.htree_workspace_bytes.argtypes = [C.POINTER(Params), C.c_int64]
     L.htree_workspace_bytes.restype = C.c_size_t
     L.htree_create.argtypes = [C.POINTER(_p), C.POINTER(Params), C.c_int64, _p, C.c_size_t, _p]
+    L.htree_batch_workspace_bytes.argtypes = [_p, _p, C.c_int32]
+    L.htree_batch_workspace_bytes.restype = C.c_size_t
+    L.htree_batch_create.argtypes = [C.POINTER(_p), _p, _p, C.c_int32, _p, C.c_size_t, _p]
+    L.htree_system_count.argtypes = [_p]
+    L.htree_system_count.restype = C.c_int32
     L.htree_set_state.argtypes = [_p, _p, _p, _p]
     L.htree_build_tree.argtypes = [_p]
     L.htree_soft_force.argtypes = [_p, _p, _p]
@@ -90,7 +95,7 @@ def lib() -> C.CDLL:
     L.htree_last_error.restype = C.c_char_p
     L.htree_destroy.argtypes = [_p]
     L.htree_destroy.restype = None
-    for name in ("htree_create", "htree_set_state", "htree_build_tree", "htree_soft_force",
+    for name in ("htree_create", "htree_batch_create", "htree_set_state", "htree_build_tree", "htree_soft_force",
                  "htree_hard_force", "htree_kick_drift", "htree_step", "htree_get_state",
                  "htree_sync", "htree_stats", "htree_group_counts", "htree_export_keys",
                  "htree_export_nodes", "htree_export_groups"):
@@ -116,3 +121,16 @@ def default_params(**kw) -> Params:
 
 def workspace_bytes(p: Params, n: int) -> int:
     return int(lib().htree_workspace_bytes(C.byref(p), int(n)))
+
+
+def batch_arrays(params, sizes):
+    """ctypes arrays (Params[S], int64[S]) for the batch entry points."""
+    S = len(sizes)
+    if len(params) != S:
+        raise ValueError("one Params per system")
+    return (Params * S)(*params), (C.c_int64 * S)(*[int(v) for v in sizes])
+
+
+def batch_workspace_bytes(params, sizes) -> int:
+    pa, na = batch_arrays(params, sizes)
+    return int(lib().htree_batch_workspace_bytes(pa, na, len(sizes)))

@@ -1,6 +1,7 @@
 // api.hip -- host implementation of the C ABI declared in include/htree.h:
 // parameter validation, workspace carving, stream-ordered orchestration of
-// the build / force / integrator kernels, status and counters.
+// the build / force / integrator kernels, status and counters.  A context
+// holds S >= 1 systems (htree_create is the case S = 1).
 #include "../../include/htree.h"
 #include "htree_dev.h"
 
@@ -36,15 +37,17 @@ htree_status fail(htree_status code, const char *fmt, ...) {
             return fail(HTREE_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_));          \
     } while (0)
 
-constexpr int64_t kMaxN = (int64_t)1 << 27;
+constexpr int64_t kMaxN = (int64_t)1 << 27;      // particles per context
+constexpr int32_t kMaxSys = 1 << 16;             // systems per context
+constexpr int64_t kChunk = 1 << 16;              // bounding-box chunk
 
 bool is_fin(double v) { return isfinite(v) != 0; }
 
-htree_status validate(const htree_params *p, int64_t n) {
-    if (!p) return fail(HTREE_EINVAL, "params is NULL");
+htree_status validate_one(const htree_params *p, int64_t n) {
     if (n < 1 || n > kMaxN) return fail(HTREE_EINVAL, "n = %lld outside [1, 2^27]", (long long)n);
     if (!is_fin(p->G) || p->G <= 0) return fail(HTREE_EINVAL, "G must be finite and > 0");
-    if (!is_fin(p->eps) || p->eps < 1e-15) return fail(HTREE_EINVAL, "eps must be finite and >= 1e-15");
+    if (!is_fin(p->eps) || p->eps < 1e-15)
+        return fail(HTREE_EINVAL, "eps must be finite and >= 1e-15");
     if (!is_fin(p->theta) || p->theta < 0) return fail(HTREE_EINVAL, "theta must be >= 0");
     if (p->hybrid != 0 && p->hybrid != 1) return fail(HTREE_EINVAL, "hybrid must be 0 or 1");
     if (p->hybrid && !(is_fin(p->R1) && is_fin(p->R2) && p->R1 > 0 && p->R2 > p->R1))
@@ -52,9 +55,30 @@ htree_status validate(const htree_params *p, int64_t n) {
     if (!is_fin(p->dt_soft)) return fail(HTREE_EINVAL, "dt_soft must be finite");
     if (p->n_sub < 1 || p->n_sub > 1024) return fail(HTREE_EINVAL, "n_sub must be in [1, 1024]");
     if (p->n_crit < 1 || p->n_crit > 4096) return fail(HTREE_EINVAL, "n_crit must be in [1, 4096]");
-    if (p->group_size != 64) return fail(HTREE_EINVAL, "group_size must be 64");
+    if (p->group_size < 1 || p->group_size > 64)
+        return fail(HTREE_EINVAL, "group_size must be in [1, 64]");
     if (p->precision != 0) return fail(HTREE_EINVAL, "precision must be 0 (FP32 interactions)");
     if (p->flags & ~(HTREE_F_POT | HTREE_F_TIMING)) return fail(HTREE_EINVAL, "unknown flags");
+    return HTREE_OK;
+}
+
+// Every system is checked; the integrator and layout settings must agree.
+htree_status validate(const htree_params *p, const int64_t *n, int32_t S) {
+    if (!p || !n) return fail(HTREE_EINVAL, "params or sizes are NULL");
+    if (S < 1 || S > kMaxSys) return fail(HTREE_EINVAL, "system count %d outside [1, 65536]", S);
+    int64_t tot = 0;
+    for (int32_t s = 0; s < S; s++) {
+        htree_status st = validate_one(&p[s], n[s]);
+        if (st) return st;
+        const htree_params &a = p[0], &b = p[s];
+        if (b.dt_soft != a.dt_soft || b.n_sub != a.n_sub || b.hybrid != a.hybrid ||
+            b.n_crit != a.n_crit || b.group_size != a.group_size || b.precision != a.precision ||
+            b.flags != a.flags)
+            return fail(HTREE_EINVAL, "system %d: dt_soft, n_sub, hybrid, n_crit, group_size, "
+                                      "precision and flags must equal those of system 0", s);
+        tot += n[s];
+    }
+    if (tot > kMaxN) return fail(HTREE_EINVAL, "total particles %lld exceed 2^27", (long long)tot);
     return HTREE_OK;
 }
 
@@ -78,7 +102,10 @@ struct Carver {
 }  // namespace
 
 struct htree_ctx {
-    htree_params p;
+    htree_params p;                    // shared settings (system 0)
+    std::vector<htree_params> ps;      // per system
+    std::vector<int64_t> ns;           // particles per system
+    int32_t S = 1;
     int64_t n = 0, ng = 0;
     int device = 0;
     hipStream_t stream = nullptr;
@@ -99,13 +126,29 @@ struct htree_ctx {
 
 namespace {
 
+int64_t chunk_count(const std::vector<int64_t> &ns) {
+    int64_t c = 0;
+    for (int64_t n : ns) c += (n + kChunk - 1) / kChunk;
+    return c;
+}
+
 void carve(Carver &C, htree_ctx *c) {
     const int64_t n = c->n;
+    const int32_t S = c->S;
     BuildBufs &B = c->B;
     B.n = n;
+    B.S = S;
+    B.sysbits = 0;
+    while ((1 << B.sysbits) < S) B.sysbits++;
     B.n_crit = c->p.n_crit;
-    B.nnmax = max_nodes(n, c->p.n_crit);
+    B.nchunks = chunk_count(c->ns);
+    B.nnmax = 0;
+    for (int64_t ns : c->ns) B.nnmax += max_nodes(ns, c->p.n_crit);
     const int64_t nnmax = B.nnmax;
+    B.sys = C.take<Sys>(S);
+    B.sysf = C.take<SysF>(S);
+    B.sys_of = C.take<uint32_t>(n);
+    B.chunk = C.take<uint2>(B.nchunks);
     for (int k = 0; k < 2; k++) {
         B.x[k] = C.take<double>(3 * n);
         B.v[k] = C.take<float>(3 * n);
@@ -116,11 +159,20 @@ void carve(Carver &C, htree_ctx *c) {
         B.key[k] = C.take<uint64_t>(n);
         B.idx[k] = C.take<uint32_t>(n);
     }
+    if (S > 1) {
+        B.skey[0] = C.take<uint32_t>(n);
+        B.skey[1] = C.take<uint32_t>(n);
+        B.ktmp = C.take<uint64_t>(n);
+    } else {
+        B.skey[0] = B.skey[1] = nullptr;
+        B.ktmp = nullptr;
+    }
     B.src = C.take<double4>(n);
-    int64_t hb = 256 * sort_blocks(nnmax);
+    const int64_t nsort = nnmax > n ? nnmax : n;
+    const int64_t hb = 256 * sort_blocks(nsort);
     B.hist = C.take<uint32_t>(hb + (int64_t)scan_partials(hb));
-    B.bbox_part = C.take<double>(6 * 1024);
-    B.frame = C.take<Frame>(1);
+    B.bbox_part = C.take<double>(6 * B.nchunks);
+    B.frame = C.take<Frame>(S);
     B.status = C.take<uint32_t>(4);
     B.cpl = C.take<int8_t>(n);
     B.leaflev = C.take<int8_t>(n);
@@ -131,13 +183,19 @@ void carve(Carver &C, htree_ctx *c) {
     B.nn = C.take<uint32_t>(4);
     B.pre_key = C.take<uint32_t>(nnmax);
     B.pre_val = C.take<uint32_t>(nnmax);
-    B.lvl_key2 = C.take<uint32_t>(nnmax);
+    B.lvl_key2 = C.take<uint32_t>(nnmax > n ? nnmax : n);
     B.bfs2pre = C.take<uint32_t>(nnmax);
     B.pre2bfs = C.take<uint32_t>(nnmax);
     B.pre_first = C.take<uint32_t>(nnmax);
     B.pre_count = C.take<uint32_t>(nnmax);
+    if (B.sysbits + 5 > 8) {
+        B.ptmp_k = C.take<uint32_t>(nnmax);
+        B.ptmp_v = C.take<uint32_t>(nnmax);
+    } else {
+        B.ptmp_k = B.ptmp_v = nullptr;
+    }
     B.node = C.take<Node>(nnmax);
-    B.S = C.take<double>(3 * nnmax);
+    B.S3 = C.take<double>(3 * nnmax);
     B.lstart = C.take<uint32_t>(kMaxLevel + 2);
     B.gstart = C.take<uint32_t>(n + 1);
     B.ng = C.take<uint32_t>(4);
@@ -148,13 +206,63 @@ void carve(Carver &C, htree_ctx *c) {
     c->tally = C.take<unsigned long long>(4);
 }
 
-size_t footprint(const htree_params *p, int64_t n) {
+void setup_sizes(htree_ctx *c, const htree_params *p, const int64_t *n, int32_t S) {
+    c->S = S;
+    c->ps.assign(p, p + S);
+    c->ns.assign(n, n + S);
+    c->p = p[0];
+    c->n = 0;
+    for (int32_t s = 0; s < S; s++) c->n += n[s];
+}
+
+size_t footprint(const htree_params *p, const int64_t *n, int32_t S) {
     htree_ctx tmp;
-    tmp.p = *p;
-    tmp.n = n;
+    setup_sizes(&tmp, p, n, S);
     Carver C{nullptr};
     carve(C, &tmp);
     return (C.off + 255) & ~(size_t)255;
+}
+
+// Host-side static tables, uploaded once at creation.
+htree_status upload_tables(htree_ctx *c) {
+    const int32_t S = c->S;
+    std::vector<Sys> sys(S);
+    std::vector<SysF> sysf(S);
+    std::vector<uint2> chunks;
+    uint32_t p0 = 0;
+    for (int32_t s = 0; s < S; s++) {
+        const htree_params &q = c->ps[s];
+        Sys &y = sys[s];
+        y.p0 = p0;
+        y.p1 = p0 + (uint32_t)c->ns[s];
+        y.c0 = (uint32_t)chunks.size();
+        for (int64_t a = y.p0; a < y.p1; a += kChunk) {
+            int64_t b = a + kChunk < y.p1 ? a + kChunk : y.p1;
+            chunks.push_back(make_uint2((uint32_t)a, (uint32_t)b));
+        }
+        y.c1 = (uint32_t)chunks.size();
+        y.invth2 = 1.0 / (q.theta * q.theta);
+        y.R2 = q.hybrid ? q.R2 : 0.0;
+        SysF &f = sysf[s];
+        f.G = (float)q.G;
+        f.eps2 = (float)(q.eps * q.eps);
+        f.R2f = (float)q.R2;
+        f.invdR = q.hybrid ? (float)(1.0 / (q.R2 - q.R1)) : 0.0f;
+        f.R2sq = q.R2 * q.R2;
+        f.Gd = q.G;
+        f.eps2d = q.eps * q.eps;
+        f.R2d = q.R2;
+        f.invdR64 = q.hybrid ? 1.0 / (q.R2 - q.R1) : 0.0;
+        p0 = y.p1;
+    }
+    BuildBufs &B = c->B;
+    HIP_OK(hipMemcpy(B.sys, sys.data(), sizeof(Sys) * S, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(B.sysf, sysf.data(), sizeof(SysF) * S, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(B.chunk, chunks.data(), sizeof(uint2) * chunks.size(),
+                     hipMemcpyHostToDevice));
+    launch_sys_of(B, c->stream);
+    HIP_OK(hipGetLastError());
+    return HTREE_OK;
 }
 
 ForceArgs force_args(htree_ctx *c) {
@@ -163,20 +271,12 @@ ForceArgs force_args(htree_ctx *c) {
     A.node = B.node;
     A.gstart = B.gstart;
     A.ng = B.ng;
+    A.sys_of = B.sys_of;
+    A.sysf = B.sysf;
     A.src = B.src;
     A.x = B.x[B.cur];
     A.frame = B.frame;
     A.n = c->n;
-    A.g = c->p.group_size;
-    A.G = (float)c->p.G;
-    A.eps2 = (float)(c->p.eps * c->p.eps);
-    A.R2f = (float)c->p.R2;
-    A.invdR = c->p.hybrid ? (float)(1.0 / (c->p.R2 - c->p.R1)) : 0.0f;
-    A.R2sq = c->p.R2 * c->p.R2;
-    A.Gd = c->p.G;
-    A.eps2d = c->p.eps * c->p.eps;
-    A.R2d = c->p.R2;
-    A.invdR64 = c->p.hybrid ? 1.0 / (c->p.R2 - c->p.R1) : 0.0;
     A.acc = nullptr;
     A.pot = nullptr;
     A.ngb = nullptr;
@@ -294,25 +394,28 @@ void htree_default_params(htree_params *p) {
     p->flags = 0;
 }
 
-size_t htree_workspace_bytes(const htree_params *p, int64_t n) {
-    if (validate(p, n) != HTREE_OK) return 0;
-    return footprint(p, n);
+size_t htree_batch_workspace_bytes(const htree_params *p, const int64_t *n, int32_t S) {
+    if (validate(p, n, S) != HTREE_OK) return 0;
+    return footprint(p, n, S);
 }
 
-htree_status htree_create(htree_ctx **out, const htree_params *p, int64_t n, void *ws,
-                          size_t ws_bytes, void *stream) {
+size_t htree_workspace_bytes(const htree_params *p, int64_t n) {
+    return htree_batch_workspace_bytes(p, &n, 1);
+}
+
+htree_status htree_batch_create(htree_ctx **out, const htree_params *p, const int64_t *n,
+                                int32_t S, void *ws, size_t ws_bytes, void *stream) {
     if (!out) return fail(HTREE_EINVAL, "out is NULL");
     *out = nullptr;
-    htree_status st = validate(p, n);
+    htree_status st = validate(p, n, S);
     if (st) return st;
-    size_t need = footprint(p, n);
+    size_t need = footprint(p, n, S);
     if (!ws) return fail(HTREE_EINVAL, "workspace is NULL");
     if (((uintptr_t)ws & 255u) != 0) return fail(HTREE_EINVAL, "workspace not 256-byte aligned");
     if (ws_bytes < need)
         return fail(HTREE_ENOMEM, "workspace has %zu bytes, needs %zu", ws_bytes, need);
     htree_ctx *c = new htree_ctx();
-    c->p = *p;
-    c->n = n;
+    setup_sizes(c, p, n, S);
     c->stream = (hipStream_t)stream;
     hipError_t e = hipGetDevice(&c->device);
     int cus = 0;
@@ -328,13 +431,15 @@ htree_status htree_create(htree_ctx **out, const htree_params *p, int64_t n, voi
     c->n_wg -= c->n_wg % 8;
     Carver C{(char *)ws};
     carve(C, c);
-    c->B.invth2 = 1.0 / (p->theta * p->theta);
-    c->B.R2 = p->hybrid ? p->R2 : 0.0;
     c->B.cur = 0;
-    c->timing = (p->flags & HTREE_F_TIMING) != 0;
+    c->timing = (p[0].flags & HTREE_F_TIMING) != 0;
     launch_zero_u32(c->B.status, 4, c->stream);
-    launch_zero_u32((uint32_t *)c->tally, 8, c->stream);
     launch_zero_u32(c->B.nn, 4, c->stream);
+    launch_zero_u32((uint32_t *)c->tally, 8, c->stream);
+    if ((st = upload_tables(c))) {
+        delete c;
+        return st;
+    }
     e = hipGetLastError();
     if (e != hipSuccess) {
         delete c;
@@ -343,6 +448,13 @@ htree_status htree_create(htree_ctx **out, const htree_params *p, int64_t n, voi
     *out = c;
     return HTREE_OK;
 }
+
+htree_status htree_create(htree_ctx **out, const htree_params *p, int64_t n, void *ws,
+                          size_t ws_bytes, void *stream) {
+    return htree_batch_create(out, p, &n, 1, ws, ws_bytes, stream);
+}
+
+int32_t htree_system_count(htree_ctx *c) { return c ? c->S : -1; }
 
 htree_status htree_set_state(htree_ctx *c, const double *d_x, const float *d_v, const float *d_m) {
     CTX_CHECK(c);
@@ -365,15 +477,13 @@ htree_status htree_build_tree(htree_ctx *c) {
 
 htree_status htree_soft_force(htree_ctx *c, float *d_acc, float *d_pot) {
     CTX_CHECK(c);
+    if (d_pot && !(c->p.flags & HTREE_F_POT))
+        return fail(HTREE_EINVAL, "d_pot given but the context lacks HTREE_F_POT");
     htree_status st = do_soft(c);
     if (st) return st;
     const BuildBufs &B = c->B;
     if (d_acc) launch_scatter3(B.as[B.cur], B.perm[B.cur], d_acc, c->n, c->stream);
-    if (d_pot) {
-        if (!(c->p.flags & HTREE_F_POT))
-            return fail(HTREE_EINVAL, "d_pot given but the context lacks HTREE_F_POT");
-        launch_scatter1f(c->pot, B.perm[B.cur], d_pot, c->n, c->stream);
-    }
+    if (d_pot) launch_scatter1f(c->pot, B.perm[B.cur], d_pot, c->n, c->stream);
     HIP_OK(hipGetLastError());
     return HTREE_OK;
 }
@@ -479,19 +589,15 @@ htree_status htree_stats(htree_ctx *c, htree_counters *out) {
     out->hard_pairs = (int64_t)t[2];
     if (c->have_soft) {
         const int64_t n = c->n;
-        uint32_t *h = new uint32_t[3 * (size_t)ng + 1];
-        hipError_t e = hipSuccess;
-        for (int k = 0; k < 3 && e == hipSuccess; k++)
-            e = hipMemcpy(h + k * (size_t)ng, c->gcount + k * n, sizeof(uint32_t) * ng,
-                          hipMemcpyDeviceToHost);
-        if (e == hipSuccess)
-            for (int64_t k = 0; k < ng; k++) {
-                out->soft_cells += h[k];
-                out->soft_far += h[ng + k];
-                out->soft_near += h[2 * ng + k];
-            }
-        delete[] h;
-        HIP_OK(e);
+        std::vector<uint32_t> h(3 * (size_t)ng + 1);
+        for (int k = 0; k < 3; k++)
+            HIP_OK(hipMemcpy(h.data() + k * (size_t)ng, c->gcount + k * n, sizeof(uint32_t) * ng,
+                             hipMemcpyDeviceToHost));
+        for (int64_t k = 0; k < ng; k++) {
+            out->soft_cells += h[k];
+            out->soft_far += h[ng + k];
+            out->soft_near += h[2 * ng + k];
+        }
     }
     float *dst[3] = {&out->ms_build, &out->ms_soft, &out->ms_hard};
     for (int k = 0; k < 3; k++) {
@@ -536,12 +642,14 @@ htree_status htree_export_keys(htree_ctx *c, uint64_t *keys, int32_t *perm, doub
     if (perm)
         HIP_OK(hipMemcpy(perm, B.perm[B.cur], sizeof(int32_t) * c->n, hipMemcpyDeviceToHost));
     if (frame4) {
-        Frame F;
-        HIP_OK(hipMemcpy(&F, B.frame, sizeof F, hipMemcpyDeviceToHost));
-        frame4[0] = F.lo[0];
-        frame4[1] = F.lo[1];
-        frame4[2] = F.lo[2];
-        frame4[3] = F.side;
+        std::vector<Frame> F(c->S);
+        HIP_OK(hipMemcpy(F.data(), B.frame, sizeof(Frame) * c->S, hipMemcpyDeviceToHost));
+        for (int32_t s = 0; s < c->S; s++) {
+            frame4[4 * s + 0] = F[s].lo[0];
+            frame4[4 * s + 1] = F[s].lo[1];
+            frame4[4 * s + 2] = F[s].lo[2];
+            frame4[4 * s + 3] = F[s].side;
+        }
     }
     return HTREE_OK;
 }
@@ -561,19 +669,16 @@ htree_status htree_export_nodes(htree_ctx *c, int32_t *level, int32_t *first, in
     if (!c->tree) return fail(HTREE_ESTATE, "no current tree");
     int64_t nn = htree_node_count(c);
     if (nn < 0) return fail(HTREE_EDEVICE, "cannot read the node count");
-    Node *h = new Node[nn > 0 ? nn : 1];
-    hipError_t e = hipMemcpy(h, c->B.node, sizeof(Node) * nn, hipMemcpyDeviceToHost);
-    if (e == hipSuccess)
-        for (int64_t k = 0; k < nn; k++) {
-            if (level) level[k] = (int32_t)(h[k].meta >> 8);
-            if (first) first[k] = (int32_t)h[k].first;
-            if (count) count[k] = (int32_t)h[k].count;
-            if (mass) mass[k] = h[k].M;
-            if (com)
-                for (int a = 0; a < 3; a++) com[a * nn + k] = h[k].com[a];
-        }
-    delete[] h;
-    HIP_OK(e);
+    std::vector<Node> h(nn > 0 ? nn : 1);
+    HIP_OK(hipMemcpy(h.data(), c->B.node, sizeof(Node) * nn, hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < nn; k++) {
+        if (level) level[k] = (int32_t)(h[k].meta >> 8);
+        if (first) first[k] = (int32_t)h[k].first;
+        if (count) count[k] = (int32_t)h[k].count;
+        if (mass) mass[k] = h[k].M;
+        if (com)
+            for (int a = 0; a < 3; a++) com[a * nn + k] = h[k].com[a];
+    }
     return HTREE_OK;
 }
 

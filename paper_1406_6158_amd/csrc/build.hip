@@ -1,18 +1,22 @@
 // build.hip -- octree construction on the GPU (section III.A.1 of the paper,
-// redesigned for gfx950): bounding box, 63-bit Morton keys, stable LSD radix
-// sort, state permutation, topology from the sorted keys, bottom-up moments.
+// redesigned for gfx950) for S independent systems at once: bounding boxes,
+// 63-bit Morton keys, stable LSD radix sort within each system, state
+// permutation, topology from the sorted keys, level-by-level moments, sink
+// groups.
 //
 // Topology without recursion.  The paper splits the sorted array recursively
 // by 3-bit key digits while a cell holds >= n_crit particles.  The same tree
 // is obtained in parallel: with c_i the number of leading 3-bit digits that
-// key i shares with key i-1, and D_i the largest number of digits shared by
-// the two ends of any window of n_crit consecutive keys containing i, the cell
-// of level l around particle i holds >= n_crit particles iff l <= D_i.  Hence
-// particle i's leaf is at level L_i = min(D_i + 1, 21) (0 if n < n_crit), and
-// the nodes that begin at sorted position i are the cells of levels
-// c_i + 1 .. L_i.  Enumerating them by position gives the depth-first
-// (pre-order) node sequence; a stable partition by level gives level order, in
-// which the children of a node are contiguous.
+// key i shares with key i-1 (-1 at a system's first particle), and D_i the
+// largest number of digits shared by the two ends of any window of n_crit
+// consecutive keys of the same system containing i, the cell of level l
+// around particle i holds >= n_crit particles iff l <= D_i.  Hence particle
+// i's leaf is at level L_i = min(D_i + 1, 21) (0 if the system has fewer than
+// n_crit particles), and the nodes that begin at sorted position i are the
+// cells of levels c_i + 1 .. L_i.  Enumerating them by position gives the
+// depth-first (pre-order) node sequence; a stable partition by (level,
+// system) gives level order, in which the children of a node are contiguous
+// and the root of system s is node s.
 #include "htree_dev.h"
 
 #include <math.h>
@@ -20,7 +24,7 @@
 namespace htree {
 
 // ---------------------------------------------------------------------------
-// small wave / block helpers
+// block scan helper
 // ---------------------------------------------------------------------------
 // Exclusive scan across a block of NT threads; returns the prefix and writes
 // the block total.
@@ -112,18 +116,32 @@ void launch_scan_u32(uint32_t *data, int64_t n, uint32_t *part, uint32_t *total,
 }
 
 // ---------------------------------------------------------------------------
-// bounding box, frame and keys
+// static system table: system of each particle position
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_sys_of(const Sys *sys, int S, uint32_t *sys_of) {
+    // one block per system, grid-stride over its particles
+    const int s = blockIdx.x;
+    if (s >= S) return;
+    for (uint32_t i = sys[s].p0 + threadIdx.x; i < sys[s].p1; i += 256) sys_of[i] = (uint32_t)s;
+}
+
+void launch_sys_of(BuildBufs &B, hipStream_t s) {
+    hipLaunchKernelGGL(k_sys_of, dim3((unsigned)B.S), dim3(256), 0, s, B.sys, B.S, B.sys_of);
+}
+
+// ---------------------------------------------------------------------------
+// bounding boxes, frames and keys
 // ---------------------------------------------------------------------------
 constexpr int kBoxNT = 256;
-constexpr int kBoxBlocks = 1024;
 
-__global__ __launch_bounds__(kBoxNT) void k_bbox(const double *x, int64_t n, double *part,
-                                                 uint32_t *status) {
+// One block per chunk of one system's particles.
+__global__ __launch_bounds__(kBoxNT) void k_bbox(const double *x, int64_t n, const uint2 *chunk,
+                                                 double *part, uint32_t *status) {
     __shared__ double sh[kBoxNT / 64][6];
+    const uint2 c = chunk[blockIdx.x];
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     bool bad = false;
-    for (int64_t i = (int64_t)blockIdx.x * kBoxNT + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * kBoxNT) {
+    for (uint32_t i = c.x + threadIdx.x; i < c.y; i += kBoxNT) {
         for (int a = 0; a < 3; a++) {
             double v = x[a * n + i];
             bad |= !isfinite(v);
@@ -146,18 +164,20 @@ __global__ __launch_bounds__(kBoxNT) void k_bbox(const double *x, int64_t n, dou
                 sh[0][a] = fmin(sh[0][a], sh[k][a]);
                 sh[0][3 + a] = fmax(sh[0][3 + a], sh[k][3 + a]);
             }
-        for (int a = 0; a < 6; a++) part[blockIdx.x * 6 + a] = sh[0][a];
+        for (int a = 0; a < 6; a++) part[(int64_t)blockIdx.x * 6 + a] = sh[0][a];
     }
 }
 
-__global__ __launch_bounds__(kBoxNT) void k_frame(const double *part, int nb, Frame *F,
-                                                  double R2) {
+// One block per system: reduce its chunks, then fix the build frame.
+__global__ __launch_bounds__(kBoxNT) void k_frame(const double *part, const Sys *sys,
+                                                  Frame *frames) {
     __shared__ double sh[kBoxNT / 64][6];
+    const Sys S = sys[blockIdx.x];
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int b = threadIdx.x; b < nb; b += kBoxNT)
+    for (uint32_t b = S.c0 + threadIdx.x; b < S.c1; b += kBoxNT)
         for (int a = 0; a < 3; a++) {
-            lo[a] = fmin(lo[a], part[b * 6 + a]);
-            hi[a] = fmax(hi[a], part[b * 6 + 3 + a]);
+            lo[a] = fmin(lo[a], part[(int64_t)b * 6 + a]);
+            hi[a] = fmax(hi[a], part[(int64_t)b * 6 + 3 + a]);
         }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     for (int a = 0; a < 3; a++) {
@@ -168,16 +188,13 @@ __global__ __launch_bounds__(kBoxNT) void k_frame(const double *part, int nb, Fr
         for (int a = 0; a < 3; a++) { sh[w][a] = lo[a]; sh[w][3 + a] = hi[a]; }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    for (int k = 1; k < kBoxNT / 64; k++)
-        for (int a = 0; a < 3; a++) {
-            lo[a] = fmin(sh[0][a], sh[k][a]);
-            hi[a] = fmax(sh[0][3 + a], sh[k][3 + a]);
-            sh[0][a] = lo[a];
-            sh[0][3 + a] = hi[a];
-        }
     for (int a = 0; a < 3; a++) {
         lo[a] = sh[0][a];
         hi[a] = sh[0][3 + a];
+        for (int k = 1; k < kBoxNT / 64; k++) {
+            lo[a] = fmin(lo[a], sh[k][a]);
+            hi[a] = fmax(hi[a], sh[k][3 + a]);
+        }
     }
     // extent of the build frame u = x - lo: rounding is monotone, so the
     // largest rounded difference is the rounded difference of the extremes
@@ -194,12 +211,13 @@ __global__ __launch_bounds__(kBoxNT) void k_frame(const double *part, int nb, Fr
         double f = frexp(ext, &e);
         side = (f == 0.5) ? ldexp(1.0, e - 1) : ldexp(1.0, e);
     }
-    for (int a = 0; a < 3; a++) F->lo[a] = lo[a];
-    F->side = side;
-    F->scale = ldexp(1.0, kMaxLevel) / side;
+    Frame &F = frames[blockIdx.x];
+    for (int a = 0; a < 3; a++) F.lo[a] = lo[a];
+    F.side = side;
+    F.scale = ldexp(1.0, kMaxLevel) / side;
     // slack covers the rounding of build-frame differences against FP64 x
-    double R2p = R2 + ldexp(side, -40);
-    F->R2pad2 = R2p * R2p;
+    double R2p = S.R2 + ldexp(side, -40);
+    F.R2pad2 = R2p * R2p;
 }
 
 __device__ inline uint64_t spread3(uint32_t v) {
@@ -222,15 +240,16 @@ __device__ inline uint32_t compact3(uint64_t x) {
     return (uint32_t)x;
 }
 
-__global__ __launch_bounds__(256) void k_keys(const double *x, int64_t n, const Frame *F,
-                                              uint64_t *key, uint32_t *idx) {
+__global__ __launch_bounds__(256) void k_keys(const double *x, int64_t n, const uint32_t *sys_of,
+                                              const Frame *frames, uint64_t *key, uint32_t *idx) {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    const double scale = F->scale;
+    const Frame &F = frames[sys_of[i]];
+    const double scale = F.scale;
     const uint32_t qmax = (1u << kMaxLevel) - 1u;
     uint32_t q[3];
     for (int a = 0; a < 3; a++) {
-        double u = x[a * n + i] - F->lo[a];
+        double u = x[a * n + i] - F.lo[a];
         double s = floor(u * scale);
         q[a] = (s >= (double)qmax) ? qmax : (uint32_t)s;
     }
@@ -240,13 +259,12 @@ __global__ __launch_bounds__(256) void k_keys(const double *x, int64_t n, const 
 
 void launch_bbox_keys(const BuildBufs &B, hipStream_t s) {
     int64_t n = B.n;
-    int nb = (int)((n + kBoxNT - 1) / kBoxNT);
-    if (nb > kBoxBlocks) nb = kBoxBlocks;
-    if (nb < 1) nb = 1;
     const double *x = B.x[B.cur];
-    hipLaunchKernelGGL(k_bbox, dim3(nb), dim3(kBoxNT), 0, s, x, n, B.bbox_part, B.status);
-    hipLaunchKernelGGL(k_frame, dim3(1), dim3(kBoxNT), 0, s, B.bbox_part, nb, B.frame, B.R2);
-    hipLaunchKernelGGL(k_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n,
+    hipLaunchKernelGGL(k_bbox, dim3((unsigned)B.nchunks), dim3(kBoxNT), 0, s, x, n, B.chunk,
+                       B.bbox_part, B.status);
+    hipLaunchKernelGGL(k_frame, dim3((unsigned)B.S), dim3(kBoxNT), 0, s, B.bbox_part, B.sys,
+                       B.frame);
+    hipLaunchKernelGGL(k_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, B.sys_of,
                        B.frame, B.key[0], B.idx[0]);
 }
 
@@ -278,7 +296,7 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
     __shared__ uint32_t run[256];
     __shared__ uint32_t base[256];
     __shared__ uint32_t wcnt[kSortThreads / 64][256];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, w = tid >> 6;
     const int64_t n = count_dev ? (int64_t)*count_dev : nmax;
     const int64_t tile0 = (int64_t)blockIdx.x * kSortTile;
     if (tile0 >= n) return;
@@ -314,7 +332,6 @@ __global__ __launch_bounds__(kSortThreads) void k_radix_scatter(
         run[tid] += add;
         __syncthreads();
     }
-    (void)lane;
 }
 
 template <typename K>
@@ -330,6 +347,26 @@ static void radix_pass(const K *kin, const uint32_t *vin, K *kout, uint32_t *vou
                        nmax, count_dev, shift, hist, nb, kout, vout);
 }
 
+// system of each entry of the Morton-ordered sequence, and its position
+__global__ __launch_bounds__(256) void k_sys_keys(const uint32_t *idx, const uint32_t *sys_of,
+                                                  int64_t n, uint32_t *skey, uint32_t *pos) {
+    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (p >= n) return;
+    skey[p] = sys_of[idx[p]];
+    pos[p] = (uint32_t)p;
+}
+
+// apply the per-system reordering to the Morton-ordered keys and payload
+__global__ __launch_bounds__(256) void k_apply_order(const uint32_t *pos, const uint64_t *key_in,
+                                                     const uint32_t *idx_in, int64_t n,
+                                                     uint64_t *key_out, uint32_t *idx_out) {
+    int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= n) return;
+    uint32_t p = pos[q];
+    key_out[q] = key_in[p];
+    idx_out[q] = idx_in[p];
+}
+
 void launch_sort(BuildBufs &B, hipStream_t s) {
     // keys are 63-bit: eight passes, the result lands back in buffer 0
     for (int pass = 0; pass < 8; pass++) {
@@ -337,28 +374,41 @@ void launch_sort(BuildBufs &B, hipStream_t s) {
         radix_pass<uint64_t>(B.key[a], B.idx[a], B.key[b], B.idx[b], B.hist, B.scan_part, nullptr,
                              B.n, 8 * pass, s);
     }
-}
-
-void launch_radix_u32(uint32_t *key_in, uint32_t *val_in, uint32_t *key_out, uint32_t *val_out,
-                      uint32_t *hist, const uint32_t *count_dev, int64_t nmax, int shift,
-                      hipStream_t s) {
-    // partials for the histogram scan live just past the histogram itself
-    int64_t nb = sort_blocks(nmax);
-    if (nb < 1) nb = 1;
-    radix_pass<uint32_t>(key_in, val_in, key_out, val_out, hist, hist + 256 * nb, count_dev, nmax,
-                         shift, s);
+    if (B.S > 1) {
+        // stable passes on the system index keep each system's key order and
+        // put every system back on its own particle range
+        const int64_t n = B.n;
+        unsigned gb = (unsigned)((n + 255) / 256);
+        uint32_t *pos[2] = {B.idx[1], (uint32_t *)B.key[1]};
+        hipLaunchKernelGGL(k_sys_keys, dim3(gb), dim3(256), 0, s, B.idx[0], B.sys_of, n,
+                           B.skey[0], pos[0]);
+        int cur = 0;
+        for (int sh = 0; sh < B.sysbits; sh += 8) {
+            radix_pass<uint32_t>(B.skey[cur], pos[cur], B.skey[cur ^ 1], pos[cur ^ 1], B.hist,
+                                 B.scan_part, nullptr, n, sh, s);
+            cur ^= 1;
+        }
+        // Morton keys and payload in final order go to spare buffers (ktmp
+        // holds n 64-bit keys; pos[cur ^ 1] is free), then back to buffer 0
+        hipLaunchKernelGGL(k_apply_order, dim3(gb), dim3(256), 0, s, pos[cur], B.key[0], B.idx[0],
+                           n, B.ktmp, pos[cur ^ 1]);
+        (void)hipMemcpyAsync(B.key[0], B.ktmp, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s);
+        (void)hipMemcpyAsync(B.idx[0], pos[cur ^ 1], sizeof(uint32_t) * n, hipMemcpyDeviceToDevice,
+                             s);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // permutation of the particle state into key order
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_gather(
-    const uint32_t *idx, int64_t n, const Frame *F, const double *x0, const float *v0,
-    const float *m0, const uint32_t *p0, const float *as0, const float *ah0, double *x1, float *v1,
-    float *m1, uint32_t *p1, float *as1, float *ah1, double4 *src) {
+    const uint32_t *idx, int64_t n, const uint32_t *sys_of, const Frame *frames, const double *x0,
+    const float *v0, const float *m0, const uint32_t *p0, const float *as0, const float *ah0,
+    double *x1, float *v1, float *m1, uint32_t *p1, float *as1, float *ah1, double4 *src) {
     int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n) return;
     uint32_t o = idx[p];
+    const Frame &F = frames[sys_of[p]];
     double xx[3];
     for (int a = 0; a < 3; a++) {
         xx[a] = x0[a * n + o];
@@ -370,15 +420,15 @@ __global__ __launch_bounds__(256) void k_gather(
     float mm = m0[o];
     m1[p] = mm;
     p1[p] = p0[o];
-    src[p] = make_double4(xx[0] - F->lo[0], xx[1] - F->lo[1], xx[2] - F->lo[2], (double)mm);
+    src[p] = make_double4(xx[0] - F.lo[0], xx[1] - F.lo[1], xx[2] - F.lo[2], (double)mm);
 }
 
 void launch_gather(BuildBufs &B, hipStream_t s) {
     int c = B.cur, d = c ^ 1;
     int64_t n = B.n;
     hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, B.idx[0], n,
-                       B.frame, B.x[c], B.v[c], B.m[c], B.perm[c], B.as[c], B.ah[c], B.x[d],
-                       B.v[d], B.m[d], B.perm[d], B.as[d], B.ah[d], B.src);
+                       B.sys_of, B.frame, B.x[c], B.v[c], B.m[c], B.perm[c], B.as[c], B.ah[c],
+                       B.x[d], B.v[d], B.m[d], B.perm[d], B.as[d], B.ah[d], B.src);
     B.cur = d;
 }
 
@@ -393,25 +443,30 @@ __device__ inline int common_levels(uint64_t a, uint64_t b) {
 }
 
 __global__ __launch_bounds__(256) void k_cpl(const uint64_t *key, int64_t n, int n_crit,
-                                             int8_t *cpl, int8_t *dwin) {
+                                             const uint32_t *sys_of, const Sys *sys, int8_t *cpl,
+                                             int8_t *dwin) {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
+    const Sys S = sys[sys_of[i]];
     uint64_t k = key[i];
-    cpl[i] = (int8_t)(i == 0 ? -1 : common_levels(key[i - 1], k));
-    // window starting at i
+    cpl[i] = (int8_t)((uint32_t)i == S.p0 ? -1 : common_levels(key[i - 1], k));
+    // window of n_crit keys starting at i, inside the system
     int64_t j = i + n_crit - 1;
-    dwin[i] = (int8_t)(j < n ? common_levels(k, key[j]) : -1);
+    dwin[i] = (int8_t)(j < (int64_t)S.p1 ? common_levels(k, key[j]) : -1);
 }
 
 __global__ __launch_bounds__(256) void k_leaflev(const int8_t *cpl, const int8_t *dwin, int64_t n,
-                                                 int n_crit, int8_t *leaflev, uint32_t *nstart) {
+                                                 int n_crit, const uint32_t *sys_of,
+                                                 const Sys *sys, int8_t *leaflev,
+                                                 uint32_t *nstart) {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
+    const int64_t p0 = sys[sys_of[i]].p0;
     int D = -1;
     int64_t s0 = i - n_crit + 1;
-    if (s0 < 0) s0 = 0;
+    if (s0 < p0) s0 = p0;
     for (int64_t s = s0; s <= i; s++) {
-        int d = dwin[s];   // -1 where the window runs past the end
+        int d = dwin[s];   // -1 where the window runs past the system's end
         if (d > D) D = d;
     }
     int L = D < 0 ? 0 : (D + 1 < kMaxLevel ? D + 1 : kMaxLevel);
@@ -421,20 +476,20 @@ __global__ __launch_bounds__(256) void k_leaflev(const int8_t *cpl, const int8_t
     if (i == n - 1) nstart[n] = 0u;   // the scan's total must not see stale data
 }
 
-// end of the level-lev cell that starts at sorted position i
-__device__ inline uint32_t cell_end(const uint64_t *key, int64_t n, int64_t i, int lev) {
+// end of the level-lev cell that starts at sorted position i (within [i, p1))
+__device__ inline uint32_t cell_end(const uint64_t *key, int64_t p1, int64_t i, int lev) {
     int sh = 3 * (kMaxLevel - lev);
     uint64_t P = key[i] >> sh;
     // gallop then bisect for the first j > i with a different prefix
     int64_t lo = i, step = 1, hi;
     for (;;) {
         hi = lo + step;
-        if (hi >= n) { hi = n; break; }
+        if (hi >= p1) { hi = p1; break; }
         if ((key[hi] >> sh) != P) break;
         lo = hi;
         step <<= 1;
     }
-    // key[lo] has prefix P; key[hi] differs (or hi == n)
+    // key[lo] has prefix P; key[hi] differs (or hi == p1)
     while (hi - lo > 1) {
         int64_t mid = lo + ((hi - lo) >> 1);
         if ((key[mid] >> sh) == P) lo = mid; else hi = mid;
@@ -444,17 +499,21 @@ __device__ inline uint32_t cell_end(const uint64_t *key, int64_t n, int64_t i, i
 
 __global__ __launch_bounds__(256) void k_emit_pre(const uint64_t *key, const int8_t *cpl,
                                                   const uint32_t *nstart, int64_t n,
-                                                  uint32_t *pre_key, uint32_t *pre_val,
-                                                  uint32_t *pre_first, uint32_t *pre_count) {
+                                                  const uint32_t *sys_of, const Sys *sys,
+                                                  int sysbits, uint32_t *pre_key,
+                                                  uint32_t *pre_val, uint32_t *pre_first,
+                                                  uint32_t *pre_count) {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     uint32_t p0 = nstart[i], p1 = nstart[i + 1];
+    const uint32_t s = sys_of[i];
+    const int64_t end = sys[s].p1;
     int lev = cpl[i] + 1;
     for (uint32_t p = p0; p < p1; p++, lev++) {
-        pre_key[p] = (uint32_t)lev;
+        pre_key[p] = ((uint32_t)lev << sysbits) | s;
         pre_val[p] = p;
         pre_first[p] = (uint32_t)i;
-        pre_count[p] = cell_end(key, n, i, lev) - (uint32_t)i;
+        pre_count[p] = cell_end(key, end, i, lev) - (uint32_t)i;
     }
 }
 
@@ -467,12 +526,15 @@ __global__ __launch_bounds__(256) void k_pre2bfs(const uint32_t *bfs2pre, const 
 
 __global__ __launch_bounds__(256) void k_fill_nodes(
     const uint64_t *key, const int8_t *leaflev, const uint32_t *nstart, const uint32_t *bfs2pre,
-    const uint32_t *pre2bfs, const uint32_t *lvl, const uint32_t *pre_first,
-    const uint32_t *pre_count, const uint32_t *nn, const Frame *F, double invth2, Node *node) {
+    const uint32_t *pre2bfs, const uint32_t *lkey, const uint32_t *pre_first,
+    const uint32_t *pre_count, const uint32_t *nn, const Frame *frames, const Sys *sys,
+    int sysbits, Node *node) {
     uint32_t b = blockIdx.x * 256 + threadIdx.x;
     if (b >= *nn) return;
     uint32_t p = bfs2pre[b];
-    int lev = (int)lvl[b];
+    const uint32_t k = lkey[b];
+    const int lev = (int)(k >> sysbits);
+    const uint32_t s = k & ((1u << sysbits) - 1u);
     uint32_t first = pre_first[p], count = pre_count[p];
     bool internal = lev < leaflev[first];
     uint32_t child = 0, nch = 0;
@@ -485,18 +547,20 @@ __global__ __launch_bounds__(256) void k_fill_nodes(
             if (e >= end) break;
             c = nstart[e];
         }
-        for (uint32_t k = 0; k < nch; k++) node[child + k].parent = b;
+        for (uint32_t j = 0; j < nch; j++) node[child + j].parent = b;
     }
-    if (b == 0) node[0].parent = 0;
-    double l = ldexp(F->side, -lev);
+    if (lev == 0) node[b].parent = b;
+    const Frame &F = frames[s];
+    double l = ldexp(F.side, -lev);
     uint64_t k0 = key[first];
     Node &N = node[b];
     N.first = first;
     N.count = count;
     N.child = child;
     N.meta = nch | ((uint32_t)lev << 8);
+    N.sys = s;
     N.l = l;
-    N.rb2 = (l * l) * invth2;
+    N.rb2 = (l * l) * sys[s].invth2;
     for (int a = 0; a < 3; a++) {
         uint32_t q = compact3(k0 >> (2 - a));
         N.blo[a] = (double)(q >> (kMaxLevel - lev)) * l;
@@ -507,20 +571,21 @@ __global__ __launch_bounds__(256) void k_fill_nodes(
 // and every level from 0 to the deepest one is present); entries past the
 // deepest level are set to the node count.  Each entry has a single writer:
 // the first node of its level, or the last node for the levels beyond.
-__global__ __launch_bounds__(256) void k_level_starts(const uint32_t *lvl, const uint32_t *nn_dev,
-                                                      uint32_t *lstart) {
+__global__ __launch_bounds__(256) void k_level_starts(const uint32_t *lkey, int sysbits,
+                                                      const uint32_t *nn_dev, uint32_t *lstart) {
     uint32_t b = blockIdx.x * 256 + threadIdx.x;
     uint32_t nn = *nn_dev;
     if (b >= nn) return;
-    if (b == 0 || lvl[b] != lvl[b - 1]) lstart[lvl[b]] = b;
+    uint32_t l = lkey[b] >> sysbits;
+    if (b == 0 || (lkey[b - 1] >> sysbits) != l) lstart[l] = b;
     if (b == nn - 1)
-        for (uint32_t l = lvl[b] + 1; l <= (uint32_t)kMaxLevel + 1; l++) lstart[l] = nn;
+        for (uint32_t m = l + 1; m <= (uint32_t)kMaxLevel + 1; m++) lstart[m] = nn;
 }
 
 // Moments of the nodes of one level, deepest level first: a leaf sums its
 // particles in sorted order (M += m, S = fma(m, u, S)); an internal node sums
 // its children's M and S in octant order; COM = S / M.
-__global__ __launch_bounds__(256) void k_moments_level(Node *node, const double4 *src, double *S,
+__global__ __launch_bounds__(256) void k_moments_level(Node *node, const double4 *src, double *S3,
                                                        const uint32_t *lstart, int level,
                                                        int64_t nnmax) {
     const uint32_t b0 = lstart[level], b1 = lstart[level + 1];
@@ -540,12 +605,12 @@ __global__ __launch_bounds__(256) void k_moments_level(Node *node, const double4
             for (uint32_t k = 0; k < nch; k++) {
                 uint32_t c = N.child + k;
                 M += node[c].M;
-                for (int a = 0; a < 3; a++) s[a] += S[a * nnmax + c];
+                for (int a = 0; a < 3; a++) s[a] += S3[a * nnmax + c];
             }
         }
         N.M = M;
         for (int a = 0; a < 3; a++) {
-            S[a * nnmax + b] = s[a];
+            S3[a * nnmax + b] = s[a];
             N.com[a] = (M != 0.0) ? s[a] / M : N.blo[a] + 0.5 * N.l;
         }
     }
@@ -555,32 +620,44 @@ void launch_topology(BuildBufs &B, bool moments, hipStream_t s) {
     int64_t n = B.n;
     unsigned gb = (unsigned)((n + 255) / 256);
     const uint64_t *key = B.key[0];
-    int8_t *dwin = (int8_t *)B.lvl_key2;   // scratch: reused as the level array later
-    hipLaunchKernelGGL(k_cpl, dim3(gb), dim3(256), 0, s, key, n, B.n_crit, B.cpl, dwin);
-    hipLaunchKernelGGL(k_leaflev, dim3(gb), dim3(256), 0, s, B.cpl, dwin, n, B.n_crit, B.leaflev,
-                       B.nstart);
+    int8_t *dwin = (int8_t *)B.lvl_key2;   // scratch: reused for the partitioned keys later
+    hipLaunchKernelGGL(k_cpl, dim3(gb), dim3(256), 0, s, key, n, B.n_crit, B.sys_of, B.sys, B.cpl,
+                       dwin);
+    hipLaunchKernelGGL(k_leaflev, dim3(gb), dim3(256), 0, s, B.cpl, dwin, n, B.n_crit, B.sys_of,
+                       B.sys, B.leaflev, B.nstart);
     launch_scan_u32(B.nstart, n + 1, B.scan_part, B.nn, s);
-    hipLaunchKernelGGL(k_emit_pre, dim3(gb), dim3(256), 0, s, key, B.cpl, B.nstart, n, B.pre_key,
-                       B.pre_val, B.pre_first, B.pre_count);
-    launch_radix_u32(B.pre_key, B.pre_val, B.lvl_key2, B.bfs2pre, B.hist, B.nn, B.nnmax, 0, s);
+    hipLaunchKernelGGL(k_emit_pre, dim3(gb), dim3(256), 0, s, key, B.cpl, B.nstart, n, B.sys_of,
+                       B.sys, B.sysbits, B.pre_key, B.pre_val, B.pre_first, B.pre_count);
+    // stable partition by (level, system): 5 + sysbits key bits
+    const int kbits = 5 + B.sysbits;
+    int64_t nb = sort_blocks(B.nnmax);
+    if (nb < 1) nb = 1;
+    uint32_t *hpart = B.hist + 256 * nb;
+    uint32_t *kin = B.pre_key, *vin = B.pre_val;
+    const int npass = (kbits + 7) / 8;
+    for (int pass = 0; pass < npass; pass++) {
+        const bool last = pass == npass - 1;
+        uint32_t *kout = last ? B.lvl_key2 : (kin == B.ptmp_k ? B.pre_key : B.ptmp_k);
+        uint32_t *vout = last ? B.bfs2pre : (vin == B.ptmp_v ? B.pre_val : B.ptmp_v);
+        radix_pass<uint32_t>(kin, vin, kout, vout, B.hist, hpart, B.nn, B.nnmax, 8 * pass, s);
+        kin = kout;
+        vin = vout;
+    }
     unsigned gn = (unsigned)((B.nnmax + 255) / 256);
     hipLaunchKernelGGL(k_pre2bfs, dim3(gn), dim3(256), 0, s, B.bfs2pre, B.nn, B.pre2bfs);
     hipLaunchKernelGGL(k_fill_nodes, dim3(gn), dim3(256), 0, s, key, B.leaflev, B.nstart,
                        B.bfs2pre, B.pre2bfs, B.lvl_key2, B.pre_first, B.pre_count, B.nn, B.frame,
-                       B.invth2, B.node);
+                       B.sys, B.sysbits, B.node);
     if (moments) {
-        hipLaunchKernelGGL(k_level_starts, dim3(gn), dim3(256), 0, s, B.lvl_key2, B.nn, B.lstart);
+        hipLaunchKernelGGL(k_level_starts, dim3(gn), dim3(256), 0, s, B.lvl_key2, B.sysbits, B.nn,
+                           B.lstart);
         // one grid-stride launch per level, deepest first
         unsigned gl = gn < 1024u ? gn : 1024u;
         for (int l = kMaxLevel; l >= 0; l--)
-            hipLaunchKernelGGL(k_moments_level, dim3(gl), dim3(256), 0, s, B.node, B.src, B.S,
+            hipLaunchKernelGGL(k_moments_level, dim3(gl), dim3(256), 0, s, B.node, B.src, B.S3,
                                B.lstart, l, B.nnmax);
     }
 }
-
-}  // namespace htree
-
-namespace htree {
 
 // ---------------------------------------------------------------------------
 // sink groups (the same rule as the tree contract): a cell with at most g
@@ -597,7 +674,7 @@ __global__ __launch_bounds__(256) void k_group_marks(const Node *node, const uin
     const Node &N = node[b];
     uint32_t count = N.count, nch = N.meta & 255u;
     if (count <= g) {
-        if (b == 0) flag[0] = 1u;       // the root is the only group
+        if ((N.meta >> 8) == 0) flag[N.first] = 1u;   // a small root is one group
         return;
     }
     if (nch == 0) {

@@ -105,15 +105,18 @@ __device__ inline uint32_t static_group(uint32_t k, uint32_t ng) {
 // Group setup shared by both walks.
 struct GroupCtx {
     uint32_t b0;
+    uint32_t sys;       // system of the group; its root is node `sys`
     int ns;
     bool act;
     double lo[3], hi[3], c[3];
 };
 
-__device__ inline void group_setup(const double4 *src, const uint32_t *gstart, uint32_t grp,
-                                   GroupCtx &G, double4 &me) {
+__device__ inline void group_setup(const double4 *src, const uint32_t *gstart,
+                                   const uint32_t *sys_of, uint32_t grp, GroupCtx &G,
+                                   double4 &me) {
     const int lane = __lane_id();
     G.b0 = gstart[grp];
+    G.sys = sys_of[G.b0];
     G.ns = (int)(gstart[grp + 1] - G.b0);
     G.act = lane < G.ns;
     me = src[G.act ? G.b0 + lane : G.b0];
@@ -243,19 +246,20 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS &S, uint32_t grp) {
     const uint64_t lt = lanemask_lt();
     GroupCtx G;
     double4 me;
-    group_setup(A.src, A.gstart, grp, G, me);
+    group_setup(A.src, A.gstart, A.sys_of, grp, G, me);
+    const SysF P = A.sysf[G.sys];
     const float sx = (float)(me.x - G.c[0]);
     const float sy = (float)(me.y - G.c[1]);
     const float sz = (float)(me.z - G.c[2]);
-    const double R2sq = A.R2sq;
-    const float eps2 = A.eps2;
+    const double R2sq = P.R2sq;
+    const float eps2 = P.eps2;
 
     Acc acc = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, 0.f, 0.f};
     uint32_t n_pc = 0, n_far = 0, n_near = 0;
     int top = 1, npc = 0, nfr = 0, nnr = 0;
     uint32_t avail = 1, ftot = 0, ntot = 0;
     if (lane == 0) {
-        S.sfirst[0] = 0;
+        S.sfirst[0] = G.sys;
         S.scnt[0] = 1;
     }
     __syncthreads();
@@ -352,7 +356,7 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS &S, uint32_t grp) {
                 S.tile[lane] = make_float4((float)(q.x - G.c[0]), (float)(q.y - G.c[1]),
                                            (float)(q.z - G.c[2]), (float)q.w);
                 __syncthreads();
-                eval_near<POT>(S.tile, 64, sx, sy, sz, eps2, A.R2f, A.invdR, acc);
+                eval_near<POT>(S.tile, 64, sx, sy, sz, eps2, P.R2f, P.invdR, acc);
                 __syncthreads();
                 ntot -= 64;
             }
@@ -381,20 +385,20 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS &S, uint32_t grp) {
                                        (float)(q.z - G.c[2]), (float)q.w);
         }
         __syncthreads();
-        eval_near<POT>(S.tile, want, sx, sy, sz, eps2, A.R2f, A.invdR, acc);
+        eval_near<POT>(S.tile, want, sx, sy, sz, eps2, P.R2f, P.invdR, acc);
         __syncthreads();
     }
 
     if (G.act) {
         const int64_t i = G.b0 + lane;
         const int64_t n = A.n;
-        A.acc[i] = A.G * (acc.a[0] - acc.c[0]);
-        A.acc[n + i] = A.G * (acc.a[1] - acc.c[1]);
-        A.acc[2 * n + i] = A.G * (acc.a[2] - acc.c[2]);
+        A.acc[i] = P.G * (acc.a[0] - acc.c[0]);
+        A.acc[n + i] = P.G * (acc.a[1] - acc.c[1]);
+        A.acc[2 * n + i] = P.G * (acc.a[2] - acc.c[2]);
         if (POT) {
             // the sink itself was summed once among its own leaf's particles
             kahan(acc.p, acc.pc, (float)me.w * rsq(eps2));
-            A.pot[i] = A.G * (acc.p - acc.pc);
+            A.pot[i] = P.G * (acc.p - acc.pc);
         }
     }
     if (lane == 0) {
@@ -450,13 +454,14 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
     const uint64_t lt = lanemask_lt();
     GroupCtx G;
     double4 me;
-    group_setup(A.src, A.gstart, grp, G, me);
+    group_setup(A.src, A.gstart, A.sys_of, grp, G, me);
+    const SysF P = A.sysf[G.sys];
     const int64_t n = A.n;
     const uint32_t mi = G.act ? G.b0 + lane : G.b0;
     const double xi = A.x[mi], yi = A.x[n + mi], zi = A.x[2 * n + mi];
-    const double R2sq = A.R2sq;
-    const double pad2 = A.frame->R2pad2;
-    const double eps2d = A.eps2d, R2 = A.R2d, invdR64 = A.invdR64;
+    const double R2sq = P.R2sq;
+    const double pad2 = A.frame[G.sys].R2pad2;
+    const double eps2d = P.eps2d, R2 = P.R2d, invdR64 = P.invdR64;
 
     // Accepted pairs are summed in FP64: the neighbour sum cancels strongly
     // (neighbours surround the sink), so FP32 per-pair rounding would be
@@ -467,7 +472,7 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
     int top = 1, nr = 0, nst = 0;
     uint32_t avail = 1, tot = 0;
     if (lane == 0) {
-        S.sfirst[0] = 0;
+        S.sfirst[0] = G.sys;
         S.scnt[0] = 1;
     }
     __syncthreads();
@@ -575,9 +580,9 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
 
     if (G.act) {
         const int64_t i = G.b0 + lane;
-        A.acc[i] = (float)(A.Gd * hx);
-        A.acc[n + i] = (float)(A.Gd * hy);
-        A.acc[2 * n + i] = (float)(A.Gd * hz);
+        A.acc[i] = (float)(P.Gd * hx);
+        A.acc[n + i] = (float)(P.Gd * hy);
+        A.acc[2 * n + i] = (float)(P.Gd * hz);
         if (A.ngb) A.ngb[i] = (int32_t)ngb;
     }
     uint32_t ngb_sum = wave_sum(G.act ? ngb : 0u);

@@ -1,5 +1,12 @@
 // htree_dev.h -- device data structures and launch wrappers shared by the
 // HIP translation units of libhtree (gfx950, wave64).
+//
+// A context holds S >= 1 independent particle systems.  Their particles are
+// concatenated (system s owns positions [Sys.p0, Sys.p1) in every particle
+// array, and keeps them: sorting is within systems), their tree nodes share
+// one level-ordered array (all roots first, root of system s at index s), and
+// their sink groups share one group table.  One launch per phase serves all
+// systems; a single system is the case S = 1.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,12 +32,27 @@ namespace htree {
 constexpr int kMaxLevel = 21;          // 63-bit keys: 21 levels of 3 bits
 constexpr int kWave = 64;
 
-// Build frame of one tree, written by the bounding-box kernel.
+// Build frame of one system, written by the bounding-box kernels.
 struct Frame {
     double lo[3];       // coordinate minimum
     double side;        // root cube side, a power of two >= extent
     double scale;       // 2^21 / side (exact power of two)
     double R2pad2;      // (R2 + slack)^2 for conservative neighbour pruning
+};
+
+// Per-system build parameters (device table).
+struct Sys {
+    uint32_t p0, p1;    // particle range
+    uint32_t c0, c1;    // bounding-box chunk range
+    double invth2;      // 1 / theta^2 (+inf for theta = 0)
+    double R2;          // hybrid cutoff, 0 in plain mode
+};
+
+// Per-system force parameters (device table).
+struct SysF {
+    float G, eps2, R2f, invdR;        // FP32 soft interaction
+    double R2sq;                      // exact cutoff test
+    double Gd, eps2d, R2d, invdR64;   // FP64 hard interaction
 };
 
 // One tree node in level (breadth-first) order; children of a node are
@@ -46,10 +68,9 @@ struct alignas(16) Node {
     uint32_t child;     // index of the first child (internal nodes)
     uint32_t meta;      // nchild | level << 8
     uint32_t parent;    // index of the parent (root: itself)
-    uint32_t pad;
+    uint32_t sys;       // system
 };
 static_assert(sizeof(Node) == 96, "node record layout");
-
 
 // ---------------------------------------------------------------------------
 // wavefront helpers (wave64)
@@ -79,16 +100,6 @@ __device__ inline uint32_t wave_sum(uint32_t v) {
     return v;
 }
 
-// Launch-order block index -> work item, so that each of the eight XCDs
-// (which take workgroups round-robin) walks one contiguous run of items and
-// keeps its neighbouring groups' tree nodes in its own L2.
-__device__ inline int64_t xcd_item(int64_t bid, int64_t total) {
-    const int64_t nx = 8;
-    int64_t q = total / nx, r = total % nx;
-    int64_t x = bid % nx, s = bid / nx;
-    return x * q + (x < r ? x : r) + s;
-}
-
 // Sticky device status bits.
 enum : uint32_t { kStatusNonFinite = 1u, kStatusOverflow = 2u };
 
@@ -99,12 +110,18 @@ constexpr int kSortTile = kSortThreads * kSortItems;
 
 inline int64_t sort_blocks(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
 
-// Workspace slices for one tree build (device pointers).
+// Workspace slices for the build (device pointers) and the host-side sizes.
 struct BuildBufs {
-    int64_t n;
+    int64_t n;             // particles over all systems
+    int32_t S;             // systems
+    int32_t sysbits;       // bits of a system index (0 for S = 1)
     int32_t n_crit;
-    double invth2;
-    double R2;
+    int64_t nchunks;       // bounding-box chunks
+    // static tables
+    Sys *sys;              // [S]
+    SysF *sysf;            // [S]
+    uint32_t *sys_of;      // [n] system of each particle position
+    uint2 *chunk;          // [nchunks] particle range of each bounding-box chunk
     // particle state, two copies each; cur selects the live copy
     double *x[2];          // [3][n]
     float *v[2];           // [3][n]
@@ -116,9 +133,11 @@ struct BuildBufs {
     double4 *src;          // [n] build-frame position and mass
     uint64_t *key[2];      // [n] sort keys (ping-pong)
     uint32_t *idx[2];      // [n] sort payload
-    uint32_t *hist;        // radix histograms
-    double *bbox_part;     // [nb][6]
-    Frame *frame;
+    uint32_t *skey[2];     // [n] system keys for the per-system ordering (S > 1)
+    uint64_t *ktmp;        // [n] key scratch for the per-system ordering (S > 1)
+    uint32_t *hist;        // radix histograms (+ scan partials)
+    double *bbox_part;     // [nchunks][6]
+    Frame *frame;          // [S]
     uint32_t *status;      // sticky status word
     // topology
     int8_t *cpl;           // [n] common-prefix level with the previous key
@@ -126,15 +145,16 @@ struct BuildBufs {
     uint32_t *nstart;      // [n+1] nodes starting at each position, scanned
     uint32_t *scan_part;   // scan partials
     uint32_t *nn;          // device node count
-    uint32_t *pre_key;     // [nnmax] level of each pre-order node
+    uint32_t *pre_key;     // [nnmax] (level, system) key of each pre-order node
     uint32_t *pre_val;     // [nnmax] pre-order index
-    uint32_t *lvl_key2;    // [nnmax] partitioned levels (scratch)
+    uint32_t *lvl_key2;    // [nnmax] partitioned keys
     uint32_t *bfs2pre;     // [nnmax]
     uint32_t *pre2bfs;     // [nnmax]
     uint32_t *pre_first;   // [nnmax]
     uint32_t *pre_count;   // [nnmax]
+    uint32_t *ptmp_k, *ptmp_v;  // [nnmax] partition scratch
     Node *node;            // [nnmax] level order
-    double *S;             // [3][nnmax] first mass moments
+    double *S3;            // [3][nnmax] first mass moments
     uint32_t *lstart;      // [kMaxLevel + 2] first node of each level
     int64_t nnmax;
     // sink groups
@@ -148,10 +168,7 @@ void launch_sort(BuildBufs &B, hipStream_t s);
 void launch_gather(BuildBufs &B, hipStream_t s);
 void launch_topology(BuildBufs &B, bool moments, hipStream_t s);
 void launch_groups(BuildBufs &B, int g, hipStream_t s);
-void launch_check_finite(const BuildBufs &B, hipStream_t s);
-void launch_radix_u32(uint32_t *key_in, uint32_t *val_in, uint32_t *key_out, uint32_t *val_out,
-                      uint32_t *hist, const uint32_t *count_dev, int64_t nmax, int shift,
-                      hipStream_t s);
+void launch_sys_of(BuildBufs &B, hipStream_t s);
 size_t scan_partials(int64_t n);
 void launch_scan_u32(uint32_t *data, int64_t n, uint32_t *part, uint32_t *total, hipStream_t s);
 
@@ -160,15 +177,12 @@ struct ForceArgs {
     const Node *node;
     const uint32_t *gstart;   // group k is sorted positions [gstart[k], gstart[k+1])
     const uint32_t *ng;       // device group count
+    const uint32_t *sys_of;   // [n]
+    const SysF *sysf;         // [S]
     const double4 *src;       // sorted build-frame positions and masses
     const double *x;          // [3][n] sorted FP64 positions (hard test)
-    const Frame *frame;
+    const Frame *frame;       // [S]
     int64_t n;
-    int32_t g;                // group size (64)
-    float G, eps2;
-    float R2f, invdR;         // changeover: Y = (R2 - r) * invdR
-    double R2sq;              // exact contract radius squared
-    double Gd, eps2d, R2d, invdR64;   // FP64 copies for the hard force
     float *acc;               // [3][n] sorted order output
     float *pot;               // [n] or null
     int32_t *ngb;             // [n] or null

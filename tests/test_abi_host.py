@@ -59,7 +59,7 @@ def test_workspace_monotone_and_aligned(abi):
 
 @pytest.mark.parametrize("field,value", [
     ("eps", 0.0), ("eps", float("nan")), ("G", -1.0), ("theta", -0.1), ("n_crit", 0),
-    ("group_size", 32), ("precision", 2), ("n_sub", 0), ("R1", 0.2), ("hybrid", 3),
+    ("group_size", 0), ("group_size", 65), ("precision", 2), ("n_sub", 0), ("R1", 0.2), ("hybrid", 3),
     ("flags", 64), ("dt_soft", float("inf")),
 ])
 def test_invalid_params_rejected(abi, field, value):
@@ -93,3 +93,21 @@ def test_create_rejects_small_or_misaligned_workspace(abi):
         abi.HTREE_EINVAL
     assert L.htree_create(C.byref(h), C.byref(p), n, None, need, None) == abi.HTREE_EINVAL
     assert not h.value
+
+
+def test_batch_workspace_and_validation(abi):
+    ps = [abi.default_params(eps=0.01 * (k + 1), theta=0.4 + 0.1 * k) for k in range(3)]
+    sizes = [1000, 1, 5000]
+    b = abi.batch_workspace_bytes(ps, sizes)
+    singles = sum(abi.workspace_bytes(p, n) for p, n in zip(ps, sizes))
+    assert b > 0 and b % 256 == 0
+    assert 0.5 * singles < b < 1.5 * singles
+    assert abi.batch_workspace_bytes(ps[:1], [6001]) < b * 1.2
+    # integrator and layout settings must agree across systems
+    bad = [abi.default_params(), abi.default_params(n_sub=2)]
+    assert abi.batch_workspace_bytes(bad, [10, 10]) == 0
+    assert b"n_sub" in abi.lib().htree_last_error()
+    assert abi.batch_workspace_bytes([], []) == 0
+    bad = [abi.default_params(), abi.default_params(eps=-1.0)]
+    assert abi.batch_workspace_bytes(bad, [10, 10]) == 0
+    assert abi.batch_workspace_bytes(ps[:2], [10, 0]) == 0
