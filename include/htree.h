@@ -93,9 +93,9 @@ size_t htree_workspace_bytes(const htree_params *p, int64_t n);
 
 /* Batch of S independent systems in one context (one launch per phase serves
  * all of them).  p[s] and n[s] describe system s (1 <= S <= 65536, total
- * particles <= 2^27).  G, eps, theta, R1, R2 may differ between systems;
- * dt_soft, n_sub, hybrid, n_crit, group_size, precision and flags must equal
- * those of system 0.  Particle arrays passed to the other calls concatenate
+ * particles <= 2^27).  G, eps, theta, R1, R2, n_crit and group_size may
+ * differ between systems; dt_soft, n_sub, hybrid, precision and flags must
+ * equal those of system 0.  Particle arrays passed to the other calls concatenate
  * the systems in order: system s occupies positions [n_0 + ... + n_{s-1},
  * ... + n_s) of every [3][N] or [N] array (N = total).  Systems never
  * interact.  Same errors as htree_create; 0 bytes if invalid. */
@@ -201,6 +201,97 @@ const char *htree_last_error(void);
 
 /* Releases the host context; the caller then frees the workspace. */
 void htree_destroy(htree_ctx *ctx);
+
+/* ---------------------------------------------------------------------------
+ * Request server: continuous batching of independent force solves.
+ *
+ * Not a construct of the paper: it serves many solves of the paper's force
+ * (build, soft force and, in hybrid mode, hard force, as htree_build_tree /
+ * htree_soft_force / htree_hard_force define them) of different sizes on one
+ * GPU.  Requests queue in submission order.  The head of the queue is admitted
+ * when a device slot is free (n_streams x per_stream slots) and the arena has
+ * a contiguous block of htree_solve_footprint bytes; admission is strictly in
+ * order.  An admitted request is enqueued whole on the least loaded stream, so
+ * requests on different streams overlap on the device.  Its results stay in
+ * its arena block until htree_server_release.  A request's results do not
+ * depend on what else is in flight.
+ *
+ * One host thread per server, with the server's device current.  The library
+ * allocates no device memory: the arena and the streams are the caller's and
+ * must outlive the server.  The only allocation is a small pinned host buffer
+ * (one 64-byte report per slot).
+ * ------------------------------------------------------------------------- */
+typedef struct htree_server htree_server;
+
+typedef struct {
+    int64_t submitted, admitted, completed, failed, cancelled;
+    int64_t pending;          /* queued, not yet admitted                        */
+    int64_t in_flight;        /* admitted, running on the device                 */
+    int64_t held;             /* finished, results not yet released              */
+    int64_t peak_in_flight;
+    uint64_t arena_bytes, bytes_in_use, bytes_peak;
+} htree_server_stats;
+
+typedef struct {
+    int64_t n;
+    int32_t status;           /* HTREE_OK or the solve's error                   */
+    int32_t state;            /* 0 pending, 1 running, 2 done, 3 failed          */
+    int32_t stream;           /* index of the stream it ran on, -1 if none       */
+    int32_t pad;
+    double t_submit, t_admit, t_done;   /* host clock, seconds since server
+                                           creation; t_done is when a poll saw
+                                           the solve finished                    */
+    uint64_t footprint;       /* arena bytes held                                */
+    int64_t soft_interactions, hard_candidates, hard_pairs;
+} htree_request_info;
+
+/* Arena bytes one solve of n particles with params p holds while admitted:
+ * its context workspace, acc_soft [3][n] f32, in hybrid mode acc_hard [3][n]
+ * f32 and ngb [n] i32, with HTREE_F_POT pot [n] f32, each 256-byte aligned.
+ * 0 if p or n is invalid. */
+size_t htree_solve_footprint(const htree_params *p, int64_t n);
+
+/* Creates a server over the device range d_arena[0, arena_bytes) (256-byte
+ * aligned) and n_streams (1..64) caller streams (hipStream_t), with at most
+ * per_stream (1..16) requests queued on each.  EINVAL, EDEVICE. */
+htree_status htree_server_create(htree_server **srv, void *d_arena, size_t arena_bytes,
+                                 void *const *hip_streams, int32_t n_streams,
+                                 int32_t per_stream);
+
+/* Queues one solve: d_x holds the x, y and z rows of the positions, ldx >= n
+ * doubles apart (the first n of each row are used); d_m [n] f32 masses.  Both
+ * must stay valid until the request has finished.  HTREE_F_TIMING is
+ * rejected.  Writes the request id (> 0).  EINVAL for bad parameters, ENOMEM
+ * if the footprint exceeds the whole arena (never admissible).  Admits what
+ * it can before returning. */
+htree_status htree_server_submit(htree_server *srv, const htree_params *p, int64_t n,
+                                 const double *d_x, int64_t ldx, const float *d_m,
+                                 int64_t *id);
+
+/* Non-blocking: detects finished solves, admits queued ones, and writes up to
+ * max_done ids of requests that finished (or failed) since they were last
+ * reported into done[], their number into *n_done. */
+htree_status htree_server_poll(htree_server *srv, int64_t *done, int32_t max_done,
+                               int32_t *n_done);
+
+/* Information and device result pointers of a request (any output pointer
+ * may be NULL).  The arrays are in the caller's particle order and stay valid
+ * until htree_server_release; pointers that do not apply (hard results of a
+ * plain solve, pot without HTREE_F_POT, any result of an unfinished or failed
+ * request) are set to NULL.  Returns the solve's status, ESTATE while it has
+ * not finished, EINVAL for an unknown id. */
+htree_status htree_server_result(htree_server *srv, int64_t id, htree_request_info *info,
+                                 float **d_acc_soft, float **d_acc_hard, int32_t **d_ngb,
+                                 float **d_pot);
+
+/* Releases a finished request's arena block, or cancels a queued one.
+ * ESTATE while it runs; EINVAL for an unknown id. */
+htree_status htree_server_release(htree_server *srv, int64_t id);
+
+htree_status htree_server_get_stats(htree_server *srv, htree_server_stats *out);
+
+/* Waits for running solves, then frees the server (not the arena). */
+void htree_server_destroy(htree_server *srv);
 
 #ifdef __cplusplus
 }

@@ -13,9 +13,10 @@ import ctypes as C
 
 from ._abi import (F_POT, F_TIMING, HTREE_EINVAL, HTREE_ENOMEM, HTREE_EOVERFLOW, HTREE_ESTATE,
                    HTreeError, Params, Counters, batch_arrays, batch_workspace_bytes, check,
-                   default_params, lib, workspace_bytes)
+                   default_params, lib, solve_footprint, workspace_bytes)
+from .server import Server
 
-__all__ = ["HTree", "Params", "Counters", "HTreeError", "default_params", "workspace_bytes",
+__all__ = ["HTree", "Server", "solve_footprint", "Params", "Counters", "HTreeError", "default_params", "workspace_bytes",
            "batch_workspace_bytes", "lib", "F_POT", "F_TIMING", "HTREE_EINVAL", "HTREE_ENOMEM",
            "HTREE_EOVERFLOW", "HTREE_ESTATE"]
 

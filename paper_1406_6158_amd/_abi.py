@@ -50,6 +50,28 @@ class Counters(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64),
+                ("failed", C.c_int64), ("cancelled", C.c_int64), ("pending", C.c_int64),
+                ("in_flight", C.c_int64), ("held", C.c_int64), ("peak_in_flight", C.c_int64),
+                ("arena_bytes", C.c_uint64), ("bytes_in_use", C.c_uint64),
+                ("bytes_peak", C.c_uint64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class RequestInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("status", C.c_int32), ("state", C.c_int32),
+                ("stream", C.c_int32), ("pad", C.c_int32), ("t_submit", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double), ("footprint", C.c_uint64),
+                ("soft_interactions", C.c_int64), ("hard_candidates", C.c_int64),
+                ("hard_pairs", C.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 _p = C.c_void_p
 _st = C.c_int32
@@ -95,6 +117,21 @@ def lib() -> C.CDLL:
     L.htree_last_error.restype = C.c_char_p
     L.htree_destroy.argtypes = [_p]
     L.htree_destroy.restype = None
+    L.htree_solve_footprint.argtypes = [C.POINTER(Params), C.c_int64]
+    L.htree_solve_footprint.restype = C.c_size_t
+    L.htree_server_create.argtypes = [C.POINTER(_p), _p, C.c_size_t, _p, C.c_int32, C.c_int32]
+    L.htree_server_submit.argtypes = [_p, C.POINTER(Params), C.c_int64, _p, C.c_int64, _p,
+                                      C.POINTER(C.c_int64)]
+    L.htree_server_poll.argtypes = [_p, _p, C.c_int32, C.POINTER(C.c_int32)]
+    L.htree_server_result.argtypes = [_p, C.c_int64, C.POINTER(RequestInfo), C.POINTER(_p),
+                                      C.POINTER(_p), C.POINTER(_p), C.POINTER(_p)]
+    L.htree_server_release.argtypes = [_p, C.c_int64]
+    L.htree_server_get_stats.argtypes = [_p, C.POINTER(ServerStats)]
+    L.htree_server_destroy.argtypes = [_p]
+    L.htree_server_destroy.restype = None
+    for name in ("htree_server_create", "htree_server_submit", "htree_server_poll",
+                 "htree_server_result", "htree_server_release", "htree_server_get_stats"):
+        getattr(L, name).restype = _st
     for name in ("htree_create", "htree_batch_create", "htree_set_state", "htree_build_tree", "htree_soft_force",
                  "htree_hard_force", "htree_kick_drift", "htree_step", "htree_get_state",
                  "htree_sync", "htree_stats", "htree_group_counts", "htree_export_keys",
@@ -121,6 +158,10 @@ def default_params(**kw) -> Params:
 
 def workspace_bytes(p: Params, n: int) -> int:
     return int(lib().htree_workspace_bytes(C.byref(p), int(n)))
+
+
+def solve_footprint(p: Params, n: int) -> int:
+    return int(lib().htree_solve_footprint(C.byref(p), int(n)))
 
 
 def batch_arrays(params, sizes):

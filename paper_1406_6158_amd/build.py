@@ -19,7 +19,7 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 OUT = PKG / "libhtree.so"
 BUILD = ROOT / "_build"
-SOURCES = ["build.hip", "force.hip", "integrate.hip", "api.hip"]
+SOURCES = ["build.hip", "force.hip", "integrate.hip", "api.hip", "serve.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -4,6 +4,7 @@
 // holds S >= 1 systems (htree_create is the case S = 1).
 #include "../../include/htree.h"
 #include "htree_dev.h"
+#include "internal.h"
 
 #include <math.h>
 #include <stdarg.h>
@@ -29,6 +30,15 @@ htree_status fail(htree_status code, const char *fmt, ...) {
     g_err = buf;
     return code;
 }
+
+}  // namespace
+
+htree_status htree::set_error(htree_status code, const char *msg) {
+    g_err = msg;
+    return code;
+}
+
+namespace {
 
 #define HIP_OK(expr)                                                                     \
     do {                                                                                 \
@@ -72,10 +82,9 @@ htree_status validate(const htree_params *p, const int64_t *n, int32_t S) {
         if (st) return st;
         const htree_params &a = p[0], &b = p[s];
         if (b.dt_soft != a.dt_soft || b.n_sub != a.n_sub || b.hybrid != a.hybrid ||
-            b.n_crit != a.n_crit || b.group_size != a.group_size || b.precision != a.precision ||
-            b.flags != a.flags)
-            return fail(HTREE_EINVAL, "system %d: dt_soft, n_sub, hybrid, n_crit, group_size, "
-                                      "precision and flags must equal those of system 0", s);
+            b.precision != a.precision || b.flags != a.flags)
+            return fail(HTREE_EINVAL, "system %d: dt_soft, n_sub, hybrid, precision and flags "
+                                      "must equal those of system 0", s);
         tot += n[s];
     }
     if (tot > kMaxN) return fail(HTREE_EINVAL, "total particles %lld exceed 2^27", (long long)tot);
@@ -116,6 +125,9 @@ struct htree_ctx {
     uint32_t *gcount = nullptr;        // [3][n] list sizes per group (first ng used)
     unsigned long long *tally = nullptr;  // [4]
     int n_wg = 0;                      // persistent force grid
+    std::vector<Sys> h_sys;            // host copies of the static tables, kept
+    std::vector<SysF> h_sysf;          // alive until the asynchronous upload is
+    std::vector<uint2> h_chunk;        // surely done (the context's lifetime)
     bool tree = false, moments = false, have_soft = false, have_hard = false;
     bool forces_current = false;
     bool timing = false;
@@ -140,10 +152,13 @@ void carve(Carver &C, htree_ctx *c) {
     B.S = S;
     B.sysbits = 0;
     while ((1 << B.sysbits) < S) B.sysbits++;
-    B.n_crit = c->p.n_crit;
+    B.max_n_crit = 0;
     B.nchunks = chunk_count(c->ns);
     B.nnmax = 0;
-    for (int64_t ns : c->ns) B.nnmax += max_nodes(ns, c->p.n_crit);
+    for (int32_t s = 0; s < S; s++) {
+        B.nnmax += max_nodes(c->ns[s], c->ps[s].n_crit);
+        if (c->ps[s].n_crit > B.max_n_crit) B.max_n_crit = c->ps[s].n_crit;
+    }
     const int64_t nnmax = B.nnmax;
     B.sys = C.take<Sys>(S);
     B.sysf = C.take<SysF>(S);
@@ -226,9 +241,12 @@ size_t footprint(const htree_params *p, const int64_t *n, int32_t S) {
 // Host-side static tables, uploaded once at creation.
 htree_status upload_tables(htree_ctx *c) {
     const int32_t S = c->S;
-    std::vector<Sys> sys(S);
-    std::vector<SysF> sysf(S);
-    std::vector<uint2> chunks;
+    std::vector<Sys> &sys = c->h_sys;
+    std::vector<SysF> &sysf = c->h_sysf;
+    std::vector<uint2> &chunks = c->h_chunk;
+    sys.assign(S, Sys{});
+    sysf.assign(S, SysF{});
+    chunks.clear();
     uint32_t p0 = 0;
     for (int32_t s = 0; s < S; s++) {
         const htree_params &q = c->ps[s];
@@ -241,6 +259,8 @@ htree_status upload_tables(htree_ctx *c) {
             chunks.push_back(make_uint2((uint32_t)a, (uint32_t)b));
         }
         y.c1 = (uint32_t)chunks.size();
+        y.n_crit = (uint32_t)q.n_crit;
+        y.g = (uint32_t)q.group_size;
         y.invth2 = 1.0 / (q.theta * q.theta);
         y.R2 = q.hybrid ? q.R2 : 0.0;
         SysF &f = sysf[s];
@@ -256,10 +276,12 @@ htree_status upload_tables(htree_ctx *c) {
         p0 = y.p1;
     }
     BuildBufs &B = c->B;
-    HIP_OK(hipMemcpy(B.sys, sys.data(), sizeof(Sys) * S, hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(B.sysf, sysf.data(), sizeof(SysF) * S, hipMemcpyHostToDevice));
-    HIP_OK(hipMemcpy(B.chunk, chunks.data(), sizeof(uint2) * chunks.size(),
-                     hipMemcpyHostToDevice));
+    // stream-ordered: a context created while other work runs does not wait for it
+    HIP_OK(hipMemcpyAsync(B.sys, sys.data(), sizeof(Sys) * S, hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(B.sysf, sysf.data(), sizeof(SysF) * S, hipMemcpyHostToDevice,
+                          c->stream));
+    HIP_OK(hipMemcpyAsync(B.chunk, chunks.data(), sizeof(uint2) * chunks.size(),
+                          hipMemcpyHostToDevice, c->stream));
     launch_sys_of(B, c->stream);
     HIP_OK(hipGetLastError());
     return HTREE_OK;
@@ -312,7 +334,7 @@ htree_status do_build(htree_ctx *c, bool moments) {
     launch_sort(c->B, c->stream);
     launch_gather(c->B, c->stream);
     launch_topology(c->B, moments, c->stream);
-    launch_groups(c->B, c->p.group_size, c->stream);
+    launch_groups(c->B, c->stream);
     ev_end(c, 0);
     HIP_OK(hipGetLastError());
     c->tree = true;
@@ -458,15 +480,7 @@ int32_t htree_system_count(htree_ctx *c) { return c ? c->S : -1; }
 
 htree_status htree_set_state(htree_ctx *c, const double *d_x, const float *d_v, const float *d_m) {
     CTX_CHECK(c);
-    if (!d_x || !d_m) return fail(HTREE_EINVAL, "x and m are required");
-    BuildBufs &B = c->B;
-    B.cur = 0;
-    launch_set_state(d_x, d_v, d_m, B.x[0], B.v[0], B.m[0], B.perm[0], c->n, c->stream);
-    launch_zero_u32((uint32_t *)B.as[0], 3 * c->n, c->stream);
-    launch_zero_u32((uint32_t *)B.ah[0], 3 * c->n, c->stream);
-    HIP_OK(hipGetLastError());
-    c->tree = c->moments = c->have_soft = c->have_hard = c->forces_current = false;
-    return HTREE_OK;
+    return htree::ctx_set_state(c, d_x, c->n, d_v, d_m);
 }
 
 htree_status htree_build_tree(htree_ctx *c) {
@@ -565,9 +579,7 @@ htree_status htree_sync(htree_ctx *c) {
     HIP_OK(hipStreamSynchronize(c->stream));
     uint32_t st = 0;
     HIP_OK(hipMemcpy(&st, c->B.status, sizeof st, hipMemcpyDeviceToHost));
-    if (st & kStatusNonFinite) return fail(HTREE_EINVAL, "non-finite particle position");
-    if (st & kStatusOverflow) return fail(HTREE_EOVERFLOW, "device capacity exceeded");
-    return HTREE_OK;
+    return htree::status_code(st);
 }
 
 htree_status htree_stats(htree_ctx *c, htree_counters *out) {
@@ -712,3 +724,32 @@ void htree_destroy(htree_ctx *c) {
 }
 
 }  // extern "C"
+
+htree_status htree::ctx_set_state(htree_ctx *c, const double *d_x, int64_t ldx, const float *d_v,
+                                  const float *d_m) {
+    if (!d_x || !d_m) return fail(HTREE_EINVAL, "x and m are required");
+    if (ldx < c->n) return fail(HTREE_EINVAL, "x row stride %lld < n", (long long)ldx);
+    BuildBufs &B = c->B;
+    B.cur = 0;
+    launch_set_state(d_x, ldx, d_v, d_m, B.x[0], B.v[0], B.m[0], B.perm[0], c->n, c->stream);
+    launch_zero_u32((uint32_t *)B.as[0], 3 * c->n, c->stream);
+    launch_zero_u32((uint32_t *)B.ah[0], 3 * c->n, c->stream);
+    HIP_OK(hipGetLastError());
+    c->tree = c->moments = c->have_soft = c->have_hard = c->forces_current = false;
+    return HTREE_OK;
+}
+
+htree_status htree::ctx_report_async(htree_ctx *c, CtxReport *dst) {
+    // the status word and the interaction tallies, copied in stream order
+    HIP_OK(hipMemcpyAsync(&dst->status, c->B.status, sizeof(uint32_t), hipMemcpyDeviceToHost,
+                          c->stream));
+    HIP_OK(hipMemcpyAsync(dst->tally, c->tally, sizeof dst->tally, hipMemcpyDeviceToHost,
+                          c->stream));
+    return HTREE_OK;
+}
+
+htree_status htree::status_code(uint32_t word) {
+    if (word & kStatusNonFinite) return fail(HTREE_EINVAL, "non-finite particle position");
+    if (word & kStatusOverflow) return fail(HTREE_EOVERFLOW, "device capacity exceeded");
+    return HTREE_OK;
+}

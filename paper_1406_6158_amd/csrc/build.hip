@@ -442,7 +442,7 @@ __device__ inline int common_levels(uint64_t a, uint64_t b) {
     return (__clzll((long long)d) - 1) / 3;
 }
 
-__global__ __launch_bounds__(256) void k_cpl(const uint64_t *key, int64_t n, int n_crit,
+__global__ __launch_bounds__(256) void k_cpl(const uint64_t *key, int64_t n,
                                              const uint32_t *sys_of, const Sys *sys, int8_t *cpl,
                                              int8_t *dwin) {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -451,19 +451,19 @@ __global__ __launch_bounds__(256) void k_cpl(const uint64_t *key, int64_t n, int
     uint64_t k = key[i];
     cpl[i] = (int8_t)((uint32_t)i == S.p0 ? -1 : common_levels(key[i - 1], k));
     // window of n_crit keys starting at i, inside the system
-    int64_t j = i + n_crit - 1;
+    int64_t j = i + (int64_t)S.n_crit - 1;
     dwin[i] = (int8_t)(j < (int64_t)S.p1 ? common_levels(k, key[j]) : -1);
 }
 
 __global__ __launch_bounds__(256) void k_leaflev(const int8_t *cpl, const int8_t *dwin, int64_t n,
-                                                 int n_crit, const uint32_t *sys_of,
-                                                 const Sys *sys, int8_t *leaflev,
-                                                 uint32_t *nstart) {
+                                                 const uint32_t *sys_of, const Sys *sys,
+                                                 int8_t *leaflev, uint32_t *nstart) {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    const int64_t p0 = sys[sys_of[i]].p0;
+    const Sys S = sys[sys_of[i]];
+    const int64_t p0 = S.p0;
     int D = -1;
-    int64_t s0 = i - n_crit + 1;
+    int64_t s0 = i - (int64_t)S.n_crit + 1;
     if (s0 < p0) s0 = p0;
     for (int64_t s = s0; s <= i; s++) {
         int d = dwin[s];   // -1 where the window runs past the system's end
@@ -621,10 +621,9 @@ void launch_topology(BuildBufs &B, bool moments, hipStream_t s) {
     unsigned gb = (unsigned)((n + 255) / 256);
     const uint64_t *key = B.key[0];
     int8_t *dwin = (int8_t *)B.lvl_key2;   // scratch: reused for the partitioned keys later
-    hipLaunchKernelGGL(k_cpl, dim3(gb), dim3(256), 0, s, key, n, B.n_crit, B.sys_of, B.sys, B.cpl,
-                       dwin);
-    hipLaunchKernelGGL(k_leaflev, dim3(gb), dim3(256), 0, s, B.cpl, dwin, n, B.n_crit, B.sys_of,
-                       B.sys, B.leaflev, B.nstart);
+    hipLaunchKernelGGL(k_cpl, dim3(gb), dim3(256), 0, s, key, n, B.sys_of, B.sys, B.cpl, dwin);
+    hipLaunchKernelGGL(k_leaflev, dim3(gb), dim3(256), 0, s, B.cpl, dwin, n, B.sys_of, B.sys,
+                       B.leaflev, B.nstart);
     launch_scan_u32(B.nstart, n + 1, B.scan_part, B.nn, s);
     hipLaunchKernelGGL(k_emit_pre, dim3(gb), dim3(256), 0, s, key, B.cpl, B.nstart, n, B.sys_of,
                        B.sys, B.sysbits, B.pre_key, B.pre_val, B.pre_first, B.pre_count);
@@ -660,18 +659,19 @@ void launch_topology(BuildBufs &B, bool moments, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// sink groups (the same rule as the tree contract): a cell with at most g
-// particles is a group; a bigger cell is split into its children; where all
+// sink groups (the same rule as the tree contract; g is the system's group
+// size): a cell with at most g particles is a group; a bigger cell is split into its children; where all
 // children are small, consecutive children are packed while the total stays
 // <= g; a bigger leaf is cut into chunks of g.  Each node with more than g
 // particles marks the group starts among its own children; a scan turns the
 // marks into the group start table.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_group_marks(const Node *node, const uint32_t *nn_dev,
-                                                     uint32_t g, uint32_t *flag) {
+                                                     const Sys *sys, uint32_t *flag) {
     uint32_t b = blockIdx.x * 256 + threadIdx.x;
     if (b >= *nn_dev) return;
     const Node &N = node[b];
+    const uint32_t g = sys[N.sys].g;
     uint32_t count = N.count, nch = N.meta & 255u;
     if (count <= g) {
         if ((N.meta >> 8) == 0) flag[N.first] = 1u;   // a small root is one group
@@ -706,12 +706,12 @@ __global__ __launch_bounds__(256) void k_group_compact(const uint32_t *scan, int
     if (i == n - 1) gstart[scan[n]] = (uint32_t)n;
 }
 
-void launch_groups(BuildBufs &B, int g, hipStream_t s) {
+void launch_groups(BuildBufs &B, hipStream_t s) {
     int64_t n = B.n;
     uint32_t *flag = B.nstart;    // free once the topology is built
     launch_zero_u32(flag, n + 1, s);
     unsigned gn = (unsigned)((B.nnmax + 255) / 256);
-    hipLaunchKernelGGL(k_group_marks, dim3(gn), dim3(256), 0, s, B.node, B.nn, (uint32_t)g, flag);
+    hipLaunchKernelGGL(k_group_marks, dim3(gn), dim3(256), 0, s, B.node, B.nn, B.sys, flag);
     launch_scan_u32(flag, n + 1, B.scan_part, B.ng, s);
     hipLaunchKernelGGL(k_group_compact, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, flag, n,
                        B.gstart);

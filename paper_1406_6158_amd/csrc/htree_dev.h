@@ -44,6 +44,8 @@ struct Frame {
 struct Sys {
     uint32_t p0, p1;    // particle range
     uint32_t c0, c1;    // bounding-box chunk range
+    uint32_t n_crit;    // a cell splits while it holds >= n_crit particles
+    uint32_t g;         // sink group size (<= 64)
     double invth2;      // 1 / theta^2 (+inf for theta = 0)
     double R2;          // hybrid cutoff, 0 in plain mode
 };
@@ -115,7 +117,7 @@ struct BuildBufs {
     int64_t n;             // particles over all systems
     int32_t S;             // systems
     int32_t sysbits;       // bits of a system index (0 for S = 1)
-    int32_t n_crit;
+    int32_t max_n_crit;    // largest n_crit of the systems
     int64_t nchunks;       // bounding-box chunks
     // static tables
     Sys *sys;              // [S]
@@ -167,7 +169,7 @@ void launch_bbox_keys(const BuildBufs &B, hipStream_t s);
 void launch_sort(BuildBufs &B, hipStream_t s);
 void launch_gather(BuildBufs &B, hipStream_t s);
 void launch_topology(BuildBufs &B, bool moments, hipStream_t s);
-void launch_groups(BuildBufs &B, int g, hipStream_t s);
+void launch_groups(BuildBufs &B, hipStream_t s);
 void launch_sys_of(BuildBufs &B, hipStream_t s);
 size_t scan_partials(int64_t n);
 void launch_scan_u32(uint32_t *data, int64_t n, uint32_t *part, uint32_t *total, hipStream_t s);
@@ -206,8 +208,8 @@ void launch_gather3(const float *src_caller, const uint32_t *perm, float *dst_so
                     hipStream_t s);
 void launch_scatter_x(const double *x_sorted, const uint32_t *perm, double *dst, int64_t n,
                       hipStream_t s);
-void launch_set_state(const double *x, const float *v, const float *m, double *xs, float *vs,
-                      float *ms, uint32_t *perm, int64_t n, hipStream_t s);
+void launch_set_state(const double *x, int64_t ldx, const float *v, const float *m, double *xs,
+                      float *vs, float *ms, uint32_t *perm, int64_t n, hipStream_t s);
 void launch_add3(const float *a, const float *b, float *out, int64_t n, hipStream_t s);
 void launch_zero_u32(uint32_t *p, int64_t n, hipStream_t s);
 

@@ -94,22 +94,23 @@ void launch_scatter_x(const double *x_sorted, const uint32_t *perm, double *dst,
     hipLaunchKernelGGL(k_scatter_x, grid_for(n), dim3(kNT), 0, s, x_sorted, perm, dst, n);
 }
 
-__global__ __launch_bounds__(kNT) void k_set_state(const double *x, const float *v,
+__global__ __launch_bounds__(kNT) void k_set_state(const double *x, int64_t ldx, const float *v,
                                                    const float *m, double *xs, float *vs,
                                                    float *ms, uint32_t *perm, int64_t n) {
     int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
     if (i >= n) return;
     for (int a = 0; a < 3; a++) {
-        xs[a * n + i] = x[a * n + i];
+        xs[a * n + i] = x[a * ldx + i];
         vs[a * n + i] = v ? v[a * n + i] : 0.0f;
     }
     ms[i] = m[i];
     perm[i] = (uint32_t)i;
 }
 
-void launch_set_state(const double *x, const float *v, const float *m, double *xs, float *vs,
-                      float *ms, uint32_t *perm, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_set_state, grid_for(n), dim3(kNT), 0, s, x, v, m, xs, vs, ms, perm, n);
+void launch_set_state(const double *x, int64_t ldx, const float *v, const float *m, double *xs,
+                      float *vs, float *ms, uint32_t *perm, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_set_state, grid_for(n), dim3(kNT), 0, s, x, ldx, v, m, xs, vs, ms, perm,
+                       n);
 }
 
 __global__ __launch_bounds__(kNT) void k_add3(const float *a, const float *b, float *out,

@@ -21,12 +21,14 @@ def _systems(count, seed, lo=8.0, hi=12.0):
         x, v, m = (synth.plummer if model == "plummer" else synth.cold_cube)(int(n), seed * 1000 + k)
         R2 = synth.r2_for_neighbours(model, int(n), 24 + 8 * (k % 3))
         out.append(dict(x=x, v=v.astype(np.float32), m=m.astype(np.float32),
-                        eps=0.005 * (1 + k % 4), theta=0.35 + 0.1 * (k % 5), R1=R2 / 2, R2=R2))
+                        eps=0.005 * (1 + k % 4), theta=0.35 + 0.1 * (k % 5), R1=R2 / 2, R2=R2,
+                        n_crit=(16, 8, 32)[k % 3], group=(64, 32, 48, 16)[k % 4]))
     return out
 
 
 def _params(P, s, **kw):
-    return P.default_params(eps=s["eps"], theta=s["theta"], R1=s["R1"], R2=s["R2"], **kw)
+    return P.default_params(eps=s["eps"], theta=s["theta"], R1=s["R1"], R2=s["R2"],
+                            n_crit=s.get("n_crit", 16), group_size=s.get("group", 64), **kw)
 
 
 def _run(P, torch, systems, batch, **kw):
@@ -58,7 +60,8 @@ def test_batch_matches_oracle(orc):
     for k, s in enumerate(systems):
         n = s["x"].shape[1]
         m64 = s["m"].astype(np.float64)
-        T = orc.Tree(s["x"], m64, n_crit=16, theta=s["theta"])
+        # n_crit and the group size differ between the systems of the batch
+        T = orc.Tree(s["x"], m64, n_crit=s["n_crit"], theta=s["theta"], group=s["group"])
         og = T.group_starts()
         ng = len(og) - 1
         assert np.array_equal(gst[goff:goff + ng + 1].astype(np.int64) - off, og), k
