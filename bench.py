@@ -12,7 +12,16 @@ kernel), timed with HIP events recorded by the library on its stream over the
 timed steps; ``cpu_baseline`` times the FP64 oracle on the host cores on a
 bounded sample of the same workload.
 
+Two further sections run after the timed steps and are reported beside
+them: ``ensemble`` (512 independent Plummer clusters, N log-uniform in
+[2^10, 2^16], one batched context after autotuning (g, n_crit) per size
+class, against the same 512 systems run one after another as single
+contexts) and ``serving`` (Poisson arrivals at 500/s of force solves with N
+log-uniform in [2^12, 2^20], admitted by HBM footprint into the request
+server, p50/p99 latency).
+
     python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline]
+                    [--no-ensemble] [--no-serve] [--serve-requests 20000]
 """
 from __future__ import annotations
 
@@ -68,13 +77,205 @@ def cpu_baseline(wl, x, m64, seconds_hint=20.0):
                       "not included)" % (k2, ng, inter, dt, t_build)}
 
 
+def _log(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
+
+
+def _pct(v, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
+
+
+def ensemble(P, torch, steps, count=512):
+    """Batched context over `count` Plummer clusters (sizes log-uniform in
+    [2^10, 2^16], eps = 4 / N^(1/3), theta = 0.5, cutoff for ~32 neighbours,
+    4 hard substeps of 1/64 per soft step) against the same systems stepped one
+    after another as single contexts on one stream."""
+    import numpy as np
+
+    import synth
+    from paper_1406_6158_amd import autotune
+    sizes = [int(n) for n in synth.ensemble_sizes(count)]
+    _log("ensemble: %d systems, %d particles" % (len(sizes), sum(sizes)))
+    systems = []
+    for k, n in enumerate(sizes):
+        x, v, m = synth.plummer(n, 4000 + k)
+        systems.append(dict(n=n, x=torch.from_numpy(x).cuda(),
+                            v=torch.from_numpy(v.astype(np.float32)).cuda(),
+                            m=torch.from_numpy(m.astype(np.float32)).cuda()))
+
+    def mk(k, g, nc, flags=P.F_TIMING):
+        n = sizes[k]
+        R2 = synth.r2_for_neighbours("plummer", n, 32)
+        return P.default_params(eps=4.0 / n ** (1.0 / 3.0), theta=0.5, R1=R2 / 2, R2=R2,
+                                dt_soft=1.0 / 16.0, n_sub=4, hybrid=1, n_crit=nc,
+                                group_size=g, flags=flags)
+
+    table, times = autotune.tune(P, torch, systems, mk, log=_log)
+    params = [mk(k, *table[autotune.size_class(n)], flags=0) for k, n in enumerate(sizes)]
+    x = torch.cat([s["x"] for s in systems], dim=1)
+    v = torch.cat([s["v"] for s in systems], dim=1)
+    m = torch.cat([s["m"] for s in systems])
+    t = P.HTree(sizes, params)
+    t.set_state(x, v, m)
+    t.step(1)
+    t.sync()
+    t.stats()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(steps)]
+    for e0, e1 in ev:
+        e0.record(t.stream)
+        t.step(1)
+        e1.record(t.stream)
+    t.sync()
+    st = t.stats()
+    step_ms = [e0.elapsed_time(e1) for e0, e1 in ev]
+    inter = (st["soft_interactions"] + st["hard_pairs"]) / steps
+    t.close()
+    del x, v, m
+    _log("ensemble: batched step %.3f ms (p50)" % _pct(step_ms, 50))
+    # the same systems as single contexts, one after another on one stream
+    singles = []
+    for k, s in enumerate(systems):
+        h = P.HTree(s["n"], params[k])
+        h.set_state(s["x"], s["v"], s["m"])
+        singles.append(h)
+    for h in singles:
+        h.step(1)
+    torch.cuda.synchronize()
+    stream = singles[0].stream
+    start = torch.cuda.Event(enable_timing=True)
+    done = [torch.cuda.Event(enable_timing=True) for _ in singles]
+    start.record(stream)
+    for h, e in zip(singles, done):
+        h.step(1)
+        e.record(stream)
+    torch.cuda.synchronize()
+    lat = [start.elapsed_time(e) for e in done]
+    for h in singles:
+        h.close()
+    _log("ensemble: sequential total %.3f ms" % lat[-1])
+    return {
+        "workload": "%d Plummer clusters, N log-uniform in [2^10, 2^16] (seed 4), eps=4/N^(1/3), "
+                    "theta=0.5, ngb~32, n_sub=4, dt_h=1/64" % len(sizes),
+        "systems": len(sizes), "particles": sum(sizes),
+        "autotune": {"2^%d" % c: {"g": g, "n_crit": nc, "ms": times[c][(g, nc)]}
+                     for c, (g, nc) in table.items()},
+        "batched_ms_per_step": {"p50": _pct(step_ms, 50), "p99": _pct(step_ms, 99),
+                                "mean": float(np.mean(step_ms)), "steps": steps},
+        "batched_interactions_per_s": inter / (np.mean(step_ms) * 1e-3),
+        "sequential_latency_ms": {"p50": _pct(lat, 50), "p99": _pct(lat, 99),
+                                  "total": lat[-1]},
+        "sequential_over_batched": lat[-1] / float(np.mean(step_ms)),
+    }
+
+
+def serving(P, torch, n_req, warm, arena_bytes, label, pool_per_model=2):
+    """Poisson arrivals (500/s) of hybrid force solves, N log-uniform in
+    [2^12, 2^20], Plummer or cold cube, theta in [0.4, 0.7]; eps =
+    0.01 (2^20/N)^(1/3), cutoff for ~64 neighbours.  Each request's
+    positions are the first N particles of one of a few pre-drawn 2^20-particle
+    sets of its model (an i.i.d. sample's prefix is an i.i.d. sample); their
+    masses are 2^-20 each with G = 2^20/N, which gives the accelerations of N
+    equal masses of total mass 1."""
+    import numpy as np
+
+    import synth
+    nmax = 1 << 20
+    reqs = synth.serving_requests(n_req + warm)
+    pool = {}
+    for model, gen in (("plummer", synth.plummer), ("cube", synth.cold_cube)):
+        pool[model] = [torch.from_numpy(gen(nmax, 7000 + 10 * j + (model == "cube"))[0]).cuda()
+                       for j in range(pool_per_model)]
+    m_pool = torch.full((nmax,), 1.0 / nmax, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+
+    def params(r):
+        n = r["n"]
+        R2 = synth.r2_for_neighbours(r["model"], n, 64)
+        return P.default_params(G=nmax / n, eps=0.01 * (nmax / n) ** (1.0 / 3.0),
+                                theta=r["theta"], R1=R2 / 2, R2=R2, hybrid=1)
+
+    arrive = np.array([r["t"] for r in reqs])
+    done_t = np.full(len(reqs), np.nan)
+    inter = np.zeros(len(reqs))
+    idx = {}
+    srv = P.Server(arena_bytes, n_streams=4, per_stream=2)
+    k = 0
+    n_done = 0
+    max_pending = 0
+    _log("serving[%s]: %d requests (+%d warm-up), arena %.1f GiB"
+         % (label, n_req, warm, arena_bytes / 2 ** 30))
+    t0 = time.perf_counter()
+    while n_done < len(reqs):
+        now = time.perf_counter() - t0
+        while k < len(reqs) and arrive[k] <= now:
+            r = reqs[k]
+            x = pool[r["model"]][k % pool_per_model][:, :r["n"]]
+            idx[srv.submit(params(r), x, m_pool[:r["n"]])] = k
+            k += 1
+        fin = srv.poll()
+        if fin:
+            tnow = time.perf_counter() - t0
+            for rid in fin:
+                j = idx.pop(rid)
+                inf = srv.info(rid)
+                if inf["status"] != 0:
+                    raise RuntimeError("request %d failed with status %d" % (j, inf["status"]))
+                done_t[j] = tnow
+                inter[j] = inf["soft_interactions"] + inf["hard_pairs"]
+                srv.release(rid)
+                n_done += 1
+                if n_done % 2000 == 0:
+                    _log("serving[%s]: %d done" % (label, n_done))
+        max_pending = max(max_pending, k - n_done)
+    st = srv.stats()
+    srv.close()
+    sel = slice(warm, None)
+    lat = (done_t - arrive)[sel] * 1e3
+    span = np.nanmax(done_t[sel]) - arrive[warm]
+    ns = np.array([r["n"] for r in reqs])[sel]
+    return {
+        "workload": "Poisson arrivals 500/s (seed 5), N log-uniform in [2^12, 2^20], Plummer or "
+                    "cold cube, theta U[0.4, 0.7], eps=0.01(2^20/N)^(1/3), ngb~64, hybrid "
+                    "build+soft+hard per request",
+        "arena_gib": arena_bytes / 2 ** 30, "requests": n_req, "warmup_requests": warm,
+        "streams": 4, "per_stream": 2,
+        "latency_ms": {"p50": _pct(lat, 50), "p99": _pct(lat, 99), "max": float(np.max(lat)),
+                       "mean": float(np.mean(lat))},
+        "latency_ms_large_n": {"p50": _pct(lat[ns >= 1 << 18], 50),
+                               "p99": _pct(lat[ns >= 1 << 18], 99)},
+        "served_requests_per_s": n_req / span,
+        "served_interactions_per_s": float(inter[sel].sum() / span),
+        "peak_in_flight": st["peak_in_flight"], "max_outstanding": int(max_pending),
+        "arena_peak_gib": st["bytes_peak"] / 2 ** 30,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-ensemble", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--ensemble-steps", type=int, default=8)
+    ap.add_argument("--serve-requests", type=int, default=20000)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 512 MiB device copy five times (the reference "
+                         "kernel for scaling HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        a = torch.ones(1 << 27, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4,
+                          "launches": 5}))
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the force path is single-GPU by design "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -155,6 +356,14 @@ def main():
         "cpu_baseline": None,
     }
     t.close()
+    if not args.no_ensemble:
+        line["ensemble"] = ensemble(P, torch, args.ensemble_steps)
+    if not args.no_serve and args.serve_requests > 0:
+        nr = args.serve_requests
+        line["serving"] = [
+            serving(P, torch, nr, max(nr // 20, 50), 32 << 30, "32 GiB"),
+            serving(P, torch, max(nr // 4, 100), max(nr // 80, 25), 2 << 30, "2 GiB"),
+        ]
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(wl, x, m32.astype(np.float64))

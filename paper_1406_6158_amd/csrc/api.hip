@@ -297,6 +297,7 @@ ForceArgs force_args(htree_ctx *c) {
     A.sysf = B.sysf;
     A.src = B.src;
     A.x = B.x[B.cur];
+    A.m = B.m[B.cur];
     A.frame = B.frame;
     A.n = c->n;
     A.acc = nullptr;

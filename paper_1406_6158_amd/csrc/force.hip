@@ -36,7 +36,7 @@
 
 namespace htree {
 
-constexpr int kStk = 512;          // range entries
+constexpr int kStk = 448;          // range entries (16 workgroups of LDS fit a CU)
 constexpr int kStkReserve = 22;    // depth-first progress room (one range per level)
 constexpr int kPC = 128;
 constexpr int kRQ = 128;
@@ -73,12 +73,6 @@ __device__ inline float one_minus_K(float r, float R2f, float invdR) {
     return t * (w * w * w);
 }
 
-__device__ inline double rsqrt64(double s) {
-    double y = (double)rsq((float)s);
-    y = y * fma(-0.5 * s, y * y, 1.5);
-    y = y * fma(-0.5 * s, y * y, 1.5);
-    return y;
-}
 __device__ inline double K_of64(double r, double R2, double invdR) {
     double Y = (R2 - r) * invdR;
     Y = fmin(fmax(Y, 0.0), 1.0);
@@ -102,6 +96,14 @@ __device__ inline uint32_t static_group(uint32_t k, uint32_t ng) {
     return off < size ? start + off : ng;
 }
 
+// A wave-uniform double held in scalar registers.
+__device__ inline double uniform_f64(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)b);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // Group setup shared by both walks.
 struct GroupCtx {
     uint32_t b0;
@@ -122,10 +124,16 @@ __device__ inline void group_setup(const double4 *src, const uint32_t *gstart,
     me = src[G.act ? G.b0 + lane : G.b0];
     double p[3] = {me.x, me.y, me.z};
     for (int a = 0; a < 3; a++) {
-        G.lo[a] = wave_min(p[a]);
-        G.hi[a] = wave_max(p[a]);
+        G.lo[a] = uniform_f64(wave_min(p[a]));
+        G.hi[a] = uniform_f64(wave_max(p[a]));
         G.c[a] = 0.5 * (G.lo[a] + G.hi[a]);
     }
+}
+
+// A source particle as an FP32 offset from the group centre, with its mass.
+__device__ inline float4 rel_src(const double4 &q, const GroupCtx &G) {
+    return make_float4((float)(q.x - G.c[0]), (float)(q.y - G.c[1]), (float)(q.z - G.c[2]),
+                       (float)q.w);
 }
 
 // ---------------------------------------------------------------------------
@@ -234,7 +242,7 @@ __device__ inline int step_width(int top, uint32_t avail) {
 struct SoftLDS {
     uint32_t sfirst[kStk], scnt[kStk];
     float4 pc[kPC];
-    float4 tile[64];
+    float4 tile[2][64];
     uint32_t ffirst[kRQ], fcnt[kRQ];
     uint32_t nfirst[kRQ], ncnt[kRQ];
     uint32_t scan[64];
@@ -339,27 +347,43 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS &S, uint32_t grp) {
             eval_far<POT, 64>(S.pc + (npc - 64), 64, sx, sy, sz, eps2, acc);
             npc -= 64;
         }
-        while (ftot >= 64) {
-            uint32_t pi = take_items(S.ffirst, S.fcnt, nfr, 64, S.scan);
-            double4 q = A.src[pi];
-            S.tile[lane] = make_float4((float)(q.x - G.c[0]), (float)(q.y - G.c[1]),
-                                       (float)(q.z - G.c[2]), (float)q.w);
-            __syncthreads();
-            eval_far<POT, 64>(S.tile, 64, sx, sy, sz, eps2, acc);
-            __syncthreads();
+        // full particle tiles, double-buffered: the gather of the next tile
+        // is in flight while the current one is evaluated
+        if (ftot >= 64) {
+            double4 q = A.src[take_items(S.ffirst, S.fcnt, nfr, 64, S.scan)];
             ftot -= 64;
-        }
-        if (HYBRID) {
-            while (ntot >= 64) {
-                uint32_t pi = take_items(S.nfirst, S.ncnt, nnr, 64, S.scan);
-                double4 q = A.src[pi];
-                S.tile[lane] = make_float4((float)(q.x - G.c[0]), (float)(q.y - G.c[1]),
-                                           (float)(q.z - G.c[2]), (float)q.w);
+            int buf = 0;
+            for (;;) {
+                S.tile[buf][lane] = rel_src(q, G);
                 __syncthreads();
-                eval_near<POT>(S.tile, 64, sx, sy, sz, eps2, P.R2f, P.invdR, acc);
-                __syncthreads();
-                ntot -= 64;
+                const bool more = ftot >= 64;
+                if (more) {
+                    q = A.src[take_items(S.ffirst, S.fcnt, nfr, 64, S.scan)];
+                    ftot -= 64;
+                }
+                eval_far<POT, 64>(S.tile[buf], 64, sx, sy, sz, eps2, acc);
+                if (!more) break;
+                buf ^= 1;
             }
+            __syncthreads();
+        }
+        if (HYBRID && ntot >= 64) {
+            double4 q = A.src[take_items(S.nfirst, S.ncnt, nnr, 64, S.scan)];
+            ntot -= 64;
+            int buf = 0;
+            for (;;) {
+                S.tile[buf][lane] = rel_src(q, G);
+                __syncthreads();
+                const bool more = ntot >= 64;
+                if (more) {
+                    q = A.src[take_items(S.nfirst, S.ncnt, nnr, 64, S.scan)];
+                    ntot -= 64;
+                }
+                eval_near<POT>(S.tile[buf], 64, sx, sy, sz, eps2, P.R2f, P.invdR, acc);
+                if (!more) break;
+                buf ^= 1;
+            }
+            __syncthreads();
         }
     }
     // partial tiles
@@ -367,25 +391,17 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS &S, uint32_t grp) {
     if (ftot > 0) {
         int want = (int)ftot;
         uint32_t pi = take_items(S.ffirst, S.fcnt, nfr, want, S.scan);
-        if (lane < want) {
-            double4 q = A.src[pi];
-            S.tile[lane] = make_float4((float)(q.x - G.c[0]), (float)(q.y - G.c[1]),
-                                       (float)(q.z - G.c[2]), (float)q.w);
-        }
+        if (lane < want) S.tile[0][lane] = rel_src(A.src[pi], G);
         __syncthreads();
-        eval_far<POT, 0>(S.tile, want, sx, sy, sz, eps2, acc);
+        eval_far<POT, 0>(S.tile[0], want, sx, sy, sz, eps2, acc);
         __syncthreads();
     }
     if (HYBRID && ntot > 0) {
         int want = (int)ntot;
         uint32_t pi = take_items(S.nfirst, S.ncnt, nnr, want, S.scan);
-        if (lane < want) {
-            double4 q = A.src[pi];
-            S.tile[lane] = make_float4((float)(q.x - G.c[0]), (float)(q.y - G.c[1]),
-                                       (float)(q.z - G.c[2]), (float)q.w);
-        }
+        if (lane < want) S.tile[0][lane] = rel_src(A.src[pi], G);
         __syncthreads();
-        eval_near<POT>(S.tile, want, sx, sy, sz, eps2, P.R2f, P.invdR, acc);
+        eval_near<POT>(S.tile[0], want, sx, sy, sz, eps2, P.R2f, P.invdR, acc);
         __syncthreads();
     }
 
@@ -438,16 +454,48 @@ void launch_soft(const ForceArgs &A, bool hybrid, bool pot, int n_wg, hipStream_
 // ---------------------------------------------------------------------------
 // hard force
 // ---------------------------------------------------------------------------
-constexpr int kStage = 128;
+constexpr int kStkHard = 256;      // the R2 walk opens few nodes
+constexpr int kStage = 192;        // staged candidates: up to 127 waiting + one gather of 64
 
 struct HardLDS {
-    uint32_t sfirst[kStk], scnt[kStk];
-    double tx[kStage], ty[kStage], tz[kStage];
-    float tm[kStage];
-    uint32_t ti[kStage];
+    uint32_t sfirst[kStkHard], scnt[kStkHard];
+    double4 tq[kStage];            // staged candidate: master x, y, z and mass
     uint32_t rfirst[kRQ], rcnt[kRQ];
     uint32_t scan[64];
 };
+
+// Pair tests of this lane's sink against 64 staged candidates (or `cnt` < 64
+// when CNT == 0): bit s of the result is set iff candidate s lies strictly
+// inside R2 by the exact FP64 test.
+template <int CNT>
+__device__ inline uint64_t pair_tests(const double4 *t, int cnt, double xi, double yi, double zi,
+                                      double R2sq) {
+    uint64_t mask = 0;
+    if (CNT == 64) {
+#pragma unroll
+        for (int s = 0; s < 64; s++) {
+            const double4 q = t[s];
+            double dx = q.x - xi, dy = q.y - yi, dz = q.z - zi;
+            double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            mask |= (uint64_t)(r2 < R2sq) << s;
+        }
+    } else {
+        for (int s = 0; s < cnt; s++) {
+            const double4 q = t[s];
+            double dx = q.x - xi, dy = q.y - yi, dz = q.z - zi;
+            double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+            mask |= (uint64_t)(r2 < R2sq) << s;
+        }
+    }
+    return mask;
+}
+
+// 1/sqrt(s) in FP64: FP32 hardware seed (relative error about 1e-7), one
+// Newton step (error about 1e-14).
+__device__ inline double rsqrt64(double s) {
+    double y = (double)rsq((float)s);
+    return y * fma(-0.5 * s, y * y, 1.5);
+}
 
 __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
     const int lane = __lane_id();
@@ -459,14 +507,24 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
     const int64_t n = A.n;
     const uint32_t mi = G.act ? G.b0 + lane : G.b0;
     const double xi = A.x[mi], yi = A.x[n + mi], zi = A.x[2 * n + mi];
+    // box of the sinks' master positions (wave-uniform)
+    double blo[3], bhi[3];
+    {
+        const double p[3] = {xi, yi, zi};
+        for (int a = 0; a < 3; a++) {
+            blo[a] = uniform_f64(wave_min(p[a]));
+            bhi[a] = uniform_f64(wave_max(p[a]));
+        }
+    }
     const double R2sq = P.R2sq;
     const double pad2 = A.frame[G.sys].R2pad2;
     const double eps2d = P.eps2d, R2 = P.R2d, invdR64 = P.invdR64;
 
     // Accepted pairs are summed in FP64: the neighbour sum cancels strongly
     // (neighbours surround the sink), so FP32 per-pair rounding would be
-    // magnified; FP64 FMA issues at the FP32 rate on this chip and accepted
-    // pairs are few.  1/sqrt is an FP32 seed refined by two Newton steps.
+    // magnified; FP64 FMA issues at the FP32 rate on this chip.  The sink
+    // itself passes the test (r = 0) and adds exactly zero force; it is
+    // removed from the neighbour count at the end.
     double hx = 0.0, hy = 0.0, hz = 0.0;
     uint32_t ngb = 0, cand = 0;
     int top = 1, nr = 0, nst = 0;
@@ -477,63 +535,91 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
     }
     __syncthreads();
 
-    // pair tests and accepted-pair forces for the top `cnt` staged candidates
+    // tests and accepted-pair forces for the top `cnt` (<= 128) staged candidates
     auto eval_top = [&](int cnt) {
         const int base = nst - cnt;
-        uint64_t mask = 0;
-        for (int s = 0; s < cnt; s++) {
-            double dx = S.tx[base + s] - xi, dy = S.ty[base + s] - yi, dz = S.tz[base + s] - zi;
-            double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            bool in = (r2 < R2sq) & (S.ti[base + s] != mi);
-            mask |= (uint64_t)in << s;
+        uint64_t m0, m1 = 0;
+        if (cnt >= 64) {
+            m0 = pair_tests<64>(S.tq + base, 64, xi, yi, zi, R2sq);
+            if (cnt == 128) m1 = pair_tests<64>(S.tq + base + 64, 64, xi, yi, zi, R2sq);
+            else if (cnt > 64) m1 = pair_tests<0>(S.tq + base + 64, cnt - 64, xi, yi, zi, R2sq);
+        } else {
+            m0 = pair_tests<0>(S.tq + base, cnt, xi, yi, zi, R2sq);
         }
-        if (!G.act) mask = 0;
-        ngb += __popcll(mask);
-        while (mask) {
-            int s = __ffsll((long long)mask) - 1 + base;
-            mask &= mask - 1;
-            double dx = S.tx[s] - xi, dy = S.ty[s] - yi, dz = S.tz[s] - zi;
+        if (!G.act) m0 = m1 = 0;
+        ngb += __popcll(m0) + __popcll(m1);
+        while (m0 | m1) {
+            int s;
+            if (m0) {
+                s = __ffsll((long long)m0) - 1;
+                m0 &= m0 - 1;
+            } else {
+                s = 63 + __ffsll((long long)m1);
+                m1 &= m1 - 1;
+            }
+            const double4 q = S.tq[base + s];
+            double dx = q.x - xi, dy = q.y - yi, dz = q.z - zi;
             double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
             double ri = rsqrt64(r2 + eps2d);
             double r = r2 > 1e-30 ? r2 * rsqrt64(r2) : 0.0;   // K = 1 below R1 anyway
             double K = K_of64(r, R2, invdR64);
-            double f = (double)S.tm[s] * K * (ri * ri * ri);
+            double f = q.w * K * (ri * ri * ri);
             hx = fma(f, dx, hx);
             hy = fma(f, dy, hy);
             hz = fma(f, dz, hz);
         }
         cand += (uint32_t)cnt;
         nst -= cnt;
-        __syncthreads();
     };
-    // move up to 64 candidate particles from the leaf ranges into the stage,
-    // keeping those within R2 (plus slack) of the group box
-    auto stage = [&](int want) {
-        uint32_t pi = take_items(S.rfirst, S.rcnt, nr, want, S.scan);
-        bool keep = false;
-        double4 q = make_double4(0, 0, 0, 0);
+
+    // Gathers of candidate particles from the leaf ranges, in two halves so
+    // that the loads of one gather are in flight while staged pairs are
+    // evaluated: issue() takes up to 64 particles and starts their loads,
+    // finish() keeps those within R2 (plus slack) of the sink box.
+    uint32_t g_pi = 0;
+    int g_want = 0;
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    float gm = 0.0f;
+    auto issue = [&](int want) {
+        g_pi = take_items(S.rfirst, S.rcnt, nr, want, S.scan);
+        g_want = want;
         if (lane < want) {
-            q = A.src[pi];
-            double D = dist2(gap_pt(G.lo[0], G.hi[0], q.x), gap_pt(G.lo[1], G.hi[1], q.y),
-                             gap_pt(G.lo[2], G.hi[2], q.z));
+            gx = A.x[g_pi];
+            gy = A.x[n + g_pi];
+            gz = A.x[2 * n + g_pi];
+            gm = A.m[g_pi];
+        }
+        tot -= (uint32_t)want;
+    };
+    auto finish = [&]() {
+        bool keep = false;
+        if (lane < g_want) {
+            double D = dist2(gap_pt(blo[0], bhi[0], gx), gap_pt(blo[1], bhi[1], gy),
+                             gap_pt(blo[2], bhi[2], gz));
             keep = D < pad2;
         }
         uint64_t m = __ballot(keep);
-        if (keep) {
-            int o = nst + __popcll(m & lt);
-            S.tx[o] = A.x[pi];
-            S.ty[o] = A.x[n + pi];
-            S.tz[o] = A.x[2 * n + pi];
-            S.tm[o] = (float)q.w;
-            S.ti[o] = pi;
-        }
+        if (keep) S.tq[nst + __popcll(m & lt)] = make_double4(gx, gy, gz, (double)gm);
         nst += __popcll(m);
-        tot -= (uint32_t)want;
+        g_want = 0;
         __syncthreads();
+    };
+    // drains full gathers, overlapping each gather's loads with evaluation
+    auto drain = [&]() {
+        bool pending = false;
+        for (;;) {
+            if (pending) finish();
+            pending = tot >= 64;
+            if (pending) issue(64);
+            if (nst >= 128) eval_top(128);
+            if (!pending) break;
+        }
     };
 
     while (avail > 0) {
-        const int want = step_width(top, avail);
+        int want = avail < 64u ? (int)avail : 64;
+        const int room = kStkHard - kStkReserve - top;
+        if (want > room) want = room > 1 ? room : 1;
         uint32_t id = take_items(S.sfirst, S.scnt, top, want, S.scan);
         avail -= (uint32_t)want;
         const bool have = lane < want;
@@ -568,18 +654,19 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
         }
         top += __popcll(m);
         avail += wave_sum(opn ? nch : 0u);
-        HT_CHECK(top <= kStk && nr < kRQ && nst < kStage);
+        HT_CHECK(top <= kStkHard && nr < kRQ && nst < kStage);
         __syncthreads();
-        while (tot >= 64) {
-            stage(64);
-            if (nst >= 64) eval_top(64);
-        }
+        drain();
     }
-    if (tot > 0) stage((int)tot);
-    while (nst > 0) eval_top(nst < 64 ? nst : 64);
+    if (tot > 0) {
+        issue((int)tot);
+        finish();
+    }
+    while (nst > 0) eval_top(nst < 128 ? nst : 128);
 
     if (G.act) {
         const int64_t i = G.b0 + lane;
+        ngb -= 1u;    // the sink itself
         A.acc[i] = (float)(P.Gd * hx);
         A.acc[n + i] = (float)(P.Gd * hy);
         A.acc[2 * n + i] = (float)(P.Gd * hz);

@@ -183,6 +183,7 @@ struct ForceArgs {
     const SysF *sysf;         // [S]
     const double4 *src;       // sorted build-frame positions and masses
     const double *x;          // [3][n] sorted FP64 positions (hard test)
+    const float *m;           // [n] sorted masses
     const Frame *frame;       // [S]
     int64_t n;
     float *acc;               // [3][n] sorted order output
