@@ -49,7 +49,7 @@ namespace {
 
 constexpr int64_t kMaxN = (int64_t)1 << 27;      // particles per context
 constexpr int32_t kMaxSys = 1 << 16;             // systems per context
-constexpr int64_t kChunk = 1 << 16;              // bounding-box chunk
+constexpr int64_t kChunk = 1 << 12;              // bounding-box chunk (one block each)
 
 bool is_fin(double v) { return isfinite(v) != 0; }
 
@@ -124,7 +124,7 @@ struct htree_ctx {
     int32_t *ngb = nullptr;            // [n] key order
     uint32_t *gcount = nullptr;        // [3][n] list sizes per group (first ng used)
     unsigned long long *tally = nullptr;  // [4]
-    int n_wg = 0;                      // persistent force grid
+    int n_wg = 0;                      // force kernel grid
     std::vector<Sys> h_sys;            // host copies of the static tables, kept
     std::vector<SysF> h_sysf;          // alive until the asynchronous upload is
     std::vector<uint2> h_chunk;        // surely done (the context's lifetime)
@@ -448,10 +448,19 @@ htree_status htree_batch_create(htree_ctx **out, const htree_params *p, const in
         delete c;
         return fail(HTREE_EDEVICE, "device query: %s", hipGetErrorString(e));
     }
-    // persistent force kernels: as many one-wavefront workgroups as the CUs
-    // hold at once (LDS and VGPR use allow 16 per CU), a multiple of 8
-    c->n_wg = (cus > 0 ? cus : 256) * 16;
-    c->n_wg -= c->n_wg % 8;
+    // force kernels: one one-wavefront workgroup per group for groups of 16
+    // or more sinks on average (typical groups hold about 45), at least one
+    // per slot of the chip (16 per CU), a multiple of 8; workgroups past the
+    // group count exit at once, groups past the grid are taken in a
+    // grid-stride loop
+    {
+        int64_t want = c->n / 16 + c->S + 64;
+        const int64_t fill = (int64_t)(cus > 0 ? cus : 256) * 16;
+        if (want < fill) want = fill;
+        if (want > ((int64_t)1 << 30)) want = (int64_t)1 << 30;
+        want = (want + 7) & ~(int64_t)7;
+        c->n_wg = (int)want;
+    }
     Carver C{(char *)ws};
     carve(C, c);
     c->B.cur = 0;

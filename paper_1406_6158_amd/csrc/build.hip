@@ -118,15 +118,22 @@ void launch_scan_u32(uint32_t *data, int64_t n, uint32_t *part, uint32_t *total,
 // ---------------------------------------------------------------------------
 // static system table: system of each particle position
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_sys_of(const Sys *sys, int S, uint32_t *sys_of) {
-    // one block per system, grid-stride over its particles
-    const int s = blockIdx.x;
-    if (s >= S) return;
-    for (uint32_t i = sys[s].p0 + threadIdx.x; i < sys[s].p1; i += 256) sys_of[i] = (uint32_t)s;
+__global__ __launch_bounds__(256) void k_sys_of(const Sys *sys, int S, int64_t n,
+                                                uint32_t *sys_of) {
+    // one thread per particle: the last system whose range starts at or before it
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    int lo = 0, hi = S - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (sys[mid].p0 <= (uint32_t)i) lo = mid; else hi = mid - 1;
+    }
+    sys_of[i] = (uint32_t)lo;
 }
 
 void launch_sys_of(BuildBufs &B, hipStream_t s) {
-    hipLaunchKernelGGL(k_sys_of, dim3((unsigned)B.S), dim3(256), 0, s, B.sys, B.S, B.sys_of);
+    hipLaunchKernelGGL(k_sys_of, dim3((unsigned)((B.n + 255) / 256)), dim3(256), 0, s, B.sys,
+                       B.S, B.n, B.sys_of);
 }
 
 // ---------------------------------------------------------------------------

@@ -20,9 +20,9 @@
 // entries; past that the walk takes one node at a time, depth first, which
 // keeps at most one partial range per tree level (21).
 //
-// The kernels are persistent: a fixed grid (a multiple of 8 workgroups) loops
-// over the groups on a static schedule that keeps each XCD on one contiguous
-// range of groups, so neighbouring groups share tree nodes in that XCD's L2.
+// Groups are dealt to workgroups by the hardware dispatcher (see sched_group):
+// one workgroup per group for the expected group count, a grid-stride loop
+// beyond it.
 //
 // Hard force (section II.C, eq. 10): per group, a walk that opens every node
 // whose box lies within R2 (plus rounding slack) of the group box collects
@@ -81,19 +81,24 @@ __device__ inline double K_of64(double r, double R2, double invdR) {
     return t * (s * s * s);
 }
 
-// Static schedule of the persistent kernels.  The grid is a multiple of 8
-// workgroups; workgroup b sits on XCD b % 8 (the dispatcher deals workgroups
-// to the XCDs round-robin) and takes, from that XCD's contiguous share of the
-// groups, every (grid / 8)-th group starting at slot b / 8.  The group index
-// is a function of scalar values only, so the loop is wave-uniform.
-__device__ inline uint32_t static_group(uint32_t k, uint32_t ng) {
-    const uint32_t nx = 8, x = blockIdx.x & 7u, slot = blockIdx.x >> 3;
-    const uint32_t slots = gridDim.x >> 3;
-    const uint32_t q = ng / nx, r = ng % nx;
-    const uint32_t size = q + (x < r ? 1u : 0u);
-    const uint32_t start = x * q + (x < r ? x : r);
-    const uint32_t off = slot + k * slots;
-    return off < size ? start + off : ng;
+// Work distribution.  Each workgroup (one wavefront) serves the groups
+// idx = blockIdx.x + k * gridDim.x, with gridDim.x a multiple of 8.  The
+// dispatcher deals workgroups to the 8 XCDs round-robin (XCD = blockIdx % 8)
+// and, within an XCD, starts them in index order as slots free up, so a slow
+// group does not hold back the others.  sched_group maps work item idx to a
+// group so that each XCD takes runs of kRun consecutive groups (which share
+// tree nodes and particles in that XCD's L2), interleaved with the other XCDs
+// at a period of 8 * kRun groups (so the dense regions of a system, which are
+// contiguous in key order, are spread over all XCDs).  The map is a bijection
+// of [0, ng): a permutation inside each full period, the identity on the tail.
+constexpr uint32_t kRun = 16;
+
+__device__ inline uint32_t sched_group(uint32_t idx, uint32_t ng) {
+    constexpr uint32_t period = 8 * kRun;
+    const uint32_t full = ng - ng % period;
+    if (idx >= full) return idx;
+    const uint32_t r = idx % period;
+    return idx - r + (r % 8) * kRun + r / 8;
 }
 
 // A wave-uniform double held in scalar registers.
@@ -432,15 +437,16 @@ template <bool HYBRID, bool POT>
 __global__ __launch_bounds__(64) void k_soft(ForceArgs A) {
     __shared__ SoftLDS S;
     const uint32_t ng = *A.ng;
-    for (uint32_t k = 0;; k++) {
-        const uint32_t grp = static_group(k, ng);
-        if (grp >= ng) break;
+    for (uint32_t idx = blockIdx.x; idx < ng; idx += gridDim.x) {
+        const uint32_t grp = sched_group(idx, ng);
+        HT_CHECK(grp < ng);
         HT_CHECK(A.gstart[grp + 1] > A.gstart[grp] && A.gstart[grp + 1] - A.gstart[grp] <= 64);
         soft_group<HYBRID, POT>(A, S, grp);
     }
 }
 
 void launch_soft(const ForceArgs &A, bool hybrid, bool pot, int n_wg, hipStream_t s) {
+    HT_CHECK(n_wg > 0 && n_wg % 8 == 0);
     dim3 grid((unsigned)n_wg), block(64);
     if (hybrid) {
         if (pot) hipLaunchKernelGGL((k_soft<true, true>), grid, block, 0, s, A);
@@ -682,14 +688,15 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
 __global__ __launch_bounds__(64) void k_hard(ForceArgs A) {
     __shared__ HardLDS S;
     const uint32_t ng = *A.ng;
-    for (uint32_t k = 0;; k++) {
-        const uint32_t grp = static_group(k, ng);
-        if (grp >= ng) break;
+    for (uint32_t idx = blockIdx.x; idx < ng; idx += gridDim.x) {
+        const uint32_t grp = sched_group(idx, ng);
+        HT_CHECK(grp < ng);
         hard_group(A, S, grp);
     }
 }
 
 void launch_hard(const ForceArgs &A, int n_wg, hipStream_t s) {
+    HT_CHECK(n_wg > 0 && n_wg % 8 == 0);
     hipLaunchKernelGGL(k_hard, dim3((unsigned)n_wg), dim3(64), 0, s, A);
 }
 

@@ -27,6 +27,8 @@ class Server:
         import torch
         self.torch = torch
         self.device = torch.device(device)
+        if self.device.index is None:
+            self.device = torch.device(self.device.type, torch.cuda.current_device())
         with torch.cuda.device(self.device):
             self.arena = torch.empty(int(arena_bytes), dtype=torch.uint8, device=self.device)
             self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
