@@ -129,6 +129,7 @@ struct htree_ctx {
     std::vector<SysF> h_sysf;          // alive until the asynchronous upload is
     std::vector<uint2> h_chunk;        // surely done (the context's lifetime)
     bool tree = false, moments = false, have_soft = false, have_hard = false;
+    bool boxes = false;                // node boxes fit the current positions (hard walk)
     bool forces_current = false;
     bool timing = false;
     std::vector<hipEvent_t> ev[3];     // per phase: start/end pairs since the last stats
@@ -211,6 +212,7 @@ void carve(Carver &C, htree_ctx *c) {
     }
     B.node = C.take<Node>(nnmax);
     B.S3 = C.take<double>(3 * nnmax);
+    B.aabb = C.take<double>(6 * nnmax);
     B.lstart = C.take<uint32_t>(kMaxLevel + 2);
     B.gstart = C.take<uint32_t>(n + 1);
     B.ng = C.take<uint32_t>(4);
@@ -298,6 +300,8 @@ ForceArgs force_args(htree_ctx *c) {
     A.src = B.src;
     A.x = B.x[B.cur];
     A.m = B.m[B.cur];
+    A.aabb = B.aabb;
+    A.nnmax = B.nnmax;
     A.frame = B.frame;
     A.n = c->n;
     A.acc = nullptr;
@@ -339,7 +343,21 @@ htree_status do_build(htree_ctx *c, bool moments) {
     ev_end(c, 0);
     HIP_OK(hipGetLastError());
     c->tree = true;
+    c->boxes = true;
     c->moments = moments;
+    return HTREE_OK;
+}
+
+// After a drift: the node boxes are recomputed from the drifted positions over
+// the same tree (same sorted order, nodes and groups).  Enough for the hard
+// force, whose walk needs only boxes that contain the particles; the soft
+// force needs a full build.
+htree_status do_refit(htree_ctx *c) {
+    ev_begin(c, 0);
+    launch_levels(c->B, false, c->stream);
+    ev_end(c, 0);
+    HIP_OK(hipGetLastError());
+    c->boxes = true;
     return HTREE_OK;
 }
 
@@ -359,7 +377,7 @@ htree_status do_soft(htree_ctx *c) {
 
 htree_status do_hard(htree_ctx *c) {
     if (!c->p.hybrid) return fail(HTREE_EINVAL, "hard_force needs hybrid mode");
-    if (!c->tree) return fail(HTREE_ESTATE, "hard_force needs a current tree");
+    if (!c->boxes) return fail(HTREE_ESTATE, "hard_force needs a current tree");
     ForceArgs A = force_args(c);
     A.acc = c->B.ah[c->B.cur];
     A.ngb = c->ngb;
@@ -377,7 +395,7 @@ htree_status kick(htree_ctx *c, double ks, double kh, double dt_drift) {
     launch_kick_drift(B.x[k], B.v[k], ks != 0.0 ? B.as[k] : nullptr, (float)ks,
                       kh != 0.0 ? B.ah[k] : nullptr, (float)kh, dt_drift, c->n, c->stream);
     HIP_OK(hipGetLastError());
-    if (dt_drift != 0.0) c->tree = c->moments = c->forces_current = false;
+    if (dt_drift != 0.0) c->tree = c->moments = c->boxes = c->forces_current = false;
     return HTREE_OK;
 }
 
@@ -540,7 +558,7 @@ htree_status htree_kick_drift(htree_ctx *c, double dt_kick, const float *d_acc, 
                           c->stream);
     }
     HIP_OK(hipGetLastError());
-    if (dt_drift != 0.0) c->tree = c->moments = c->forces_current = false;
+    if (dt_drift != 0.0) c->tree = c->moments = c->boxes = c->forces_current = false;
     return HTREE_OK;
 }
 
@@ -564,8 +582,10 @@ htree_status htree_step(htree_ctx *c, int32_t n_soft) {
         for (int h = 0; h < nsub; h++) {
             // opening kicks (soft half-kick on the first substep) and the drift
             if ((st = kick(c, h == 0 ? 0.5 * dts : 0.0, 0.5 * dth, dth))) return st;
+            // a full build where the soft force needs it, a refit of the
+            // node boxes on the other substeps
             const bool last = h == nsub - 1;
-            if ((st = do_build(c, last))) return st;
+            if ((st = last ? do_build(c, true) : do_refit(c))) return st;
             if (last && (st = do_soft(c))) return st;
             if ((st = do_hard(c))) return st;
             if ((st = kick(c, last ? 0.5 * dts : 0.0, 0.5 * dth, 0.0))) return st;
@@ -745,7 +765,7 @@ htree_status htree::ctx_set_state(htree_ctx *c, const double *d_x, int64_t ldx, 
     launch_zero_u32((uint32_t *)B.as[0], 3 * c->n, c->stream);
     launch_zero_u32((uint32_t *)B.ah[0], 3 * c->n, c->stream);
     HIP_OK(hipGetLastError());
-    c->tree = c->moments = c->have_soft = c->have_hard = c->forces_current = false;
+    c->tree = c->moments = c->boxes = c->have_soft = c->have_hard = c->forces_current = false;
     return HTREE_OK;
 }
 

@@ -589,37 +589,78 @@ __global__ __launch_bounds__(256) void k_level_starts(const uint32_t *lkey, int 
         for (uint32_t m = l + 1; m <= (uint32_t)kMaxLevel + 1; m++) lstart[m] = nn;
 }
 
-// Moments of the nodes of one level, deepest level first: a leaf sums its
-// particles in sorted order (M += m, S = fma(m, u, S)); an internal node sums
-// its children's M and S in octant order; COM = S / M.
-__global__ __launch_bounds__(256) void k_moments_level(Node *node, const double4 *src, double *S3,
-                                                       const uint32_t *lstart, int level,
-                                                       int64_t nnmax) {
+// One level of the bottom-up pass, deepest level first.  Every node gets the
+// box of its particles' master positions (exact minima and maxima: a leaf
+// over its particles, an internal node over its children's boxes).  With
+// MOM, also the moments: a leaf sums its particles in sorted order (M += m,
+// S = fma(m, u, S)); an internal node sums its children's M and S in octant
+// order; COM = S / M.
+template <bool MOM>
+__global__ __launch_bounds__(256) void k_level_pass(Node *node, const double4 *src, const double *x,
+                                                    int64_t n, double *S3, double *aabb,
+                                                    const uint32_t *lstart, int level,
+                                                    int64_t nnmax) {
     const uint32_t b0 = lstart[level], b1 = lstart[level + 1];
     for (uint32_t b = b0 + blockIdx.x * 256 + threadIdx.x; b < b1; b += gridDim.x * 256) {
         Node &N = node[b];
-        uint32_t nch = N.meta & 255u;
+        const uint32_t nch = N.meta & 255u;
         double M = 0.0, s[3] = {0.0, 0.0, 0.0};
+        double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
         if (nch == 0) {
             for (uint32_t i = N.first; i < N.first + N.count; i++) {
-                double4 q = src[i];
-                M += q.w;
-                s[0] = fma(q.w, q.x, s[0]);
-                s[1] = fma(q.w, q.y, s[1]);
-                s[2] = fma(q.w, q.z, s[2]);
+                for (int a = 0; a < 3; a++) {
+                    const double v = x[a * n + i];
+                    lo[a] = fmin(lo[a], v);
+                    hi[a] = fmax(hi[a], v);
+                }
+                if (MOM) {
+                    const double4 q = src[i];
+                    M += q.w;
+                    s[0] = fma(q.w, q.x, s[0]);
+                    s[1] = fma(q.w, q.y, s[1]);
+                    s[2] = fma(q.w, q.z, s[2]);
+                }
             }
         } else {
             for (uint32_t k = 0; k < nch; k++) {
-                uint32_t c = N.child + k;
-                M += node[c].M;
-                for (int a = 0; a < 3; a++) s[a] += S3[a * nnmax + c];
+                const uint32_t c = N.child + k;
+                for (int a = 0; a < 3; a++) {
+                    lo[a] = fmin(lo[a], aabb[a * nnmax + c]);
+                    hi[a] = fmax(hi[a], aabb[(3 + a) * nnmax + c]);
+                }
+                if (MOM) {
+                    M += node[c].M;
+                    for (int a = 0; a < 3; a++) s[a] += S3[a * nnmax + c];
+                }
             }
         }
-        N.M = M;
         for (int a = 0; a < 3; a++) {
-            S3[a * nnmax + b] = s[a];
-            N.com[a] = (M != 0.0) ? s[a] / M : N.blo[a] + 0.5 * N.l;
+            aabb[a * nnmax + b] = lo[a];
+            aabb[(3 + a) * nnmax + b] = hi[a];
         }
+        if (MOM) {
+            N.M = M;
+            for (int a = 0; a < 3; a++) {
+                S3[a * nnmax + b] = s[a];
+                N.com[a] = (M != 0.0) ? s[a] / M : N.blo[a] + 0.5 * N.l;
+            }
+        }
+    }
+}
+
+// The bottom-up pass over all levels (lstart must be current): node boxes,
+// and moments if asked.  Also the refit of the boxes after a drift.
+void launch_levels(BuildBufs &B, bool moments, hipStream_t s) {
+    unsigned gn = (unsigned)((B.nnmax + 255) / 256);
+    unsigned gl = gn < 1024u ? gn : 1024u;
+    const double *x = B.x[B.cur];
+    for (int l = kMaxLevel; l >= 0; l--) {
+        if (moments)
+            hipLaunchKernelGGL(k_level_pass<true>, dim3(gl), dim3(256), 0, s, B.node, B.src, x,
+                               B.n, B.S3, B.aabb, B.lstart, l, B.nnmax);
+        else
+            hipLaunchKernelGGL(k_level_pass<false>, dim3(gl), dim3(256), 0, s, B.node, B.src, x,
+                               B.n, B.S3, B.aabb, B.lstart, l, B.nnmax);
     }
 }
 
@@ -654,15 +695,9 @@ void launch_topology(BuildBufs &B, bool moments, hipStream_t s) {
     hipLaunchKernelGGL(k_fill_nodes, dim3(gn), dim3(256), 0, s, key, B.leaflev, B.nstart,
                        B.bfs2pre, B.pre2bfs, B.lvl_key2, B.pre_first, B.pre_count, B.nn, B.frame,
                        B.sys, B.sysbits, B.node);
-    if (moments) {
-        hipLaunchKernelGGL(k_level_starts, dim3(gn), dim3(256), 0, s, B.lvl_key2, B.sysbits, B.nn,
-                           B.lstart);
-        // one grid-stride launch per level, deepest first
-        unsigned gl = gn < 1024u ? gn : 1024u;
-        for (int l = kMaxLevel; l >= 0; l--)
-            hipLaunchKernelGGL(k_moments_level, dim3(gl), dim3(256), 0, s, B.node, B.src, B.S3,
-                               B.lstart, l, B.nnmax);
-    }
+    hipLaunchKernelGGL(k_level_starts, dim3(gn), dim3(256), 0, s, B.lvl_key2, B.sysbits, B.nn,
+                       B.lstart);
+    launch_levels(B, moments, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -25,8 +25,9 @@
 // beyond it.
 //
 // Hard force (section II.C, eq. 10): per group, a walk that opens every node
-// whose box lies within R2 (plus rounding slack) of the group box collects
-// candidate leaves; their particles are filtered against the group box, then
+// whose box (the bounding box of its particles' master positions, kept
+// current by a refit after each drift) lies within R2 (plus rounding slack)
+// of the group box collects candidate leaves; their particles are filtered against the group box, then
 // every candidate pair is decided by the exact FP64 test
 // fma(dz,dz, fma(dy,dy, dx*dx)) < R2^2 on the master positions, and accepted
 // pairs add K(r) times the softened pair force, summed in FP64.
@@ -506,14 +507,16 @@ __device__ inline double rsqrt64(double s) {
 __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
     const int lane = __lane_id();
     const uint64_t lt = lanemask_lt();
-    GroupCtx G;
-    double4 me;
-    group_setup(A.src, A.gstart, A.sys_of, grp, G, me);
-    const SysF P = A.sysf[G.sys];
+    const uint32_t b0 = A.gstart[grp];
+    const uint32_t sys = A.sys_of[b0];
+    const int ns = (int)(A.gstart[grp + 1] - b0);
+    const bool act = lane < ns;
+    const SysF P = A.sysf[sys];
     const int64_t n = A.n;
-    const uint32_t mi = G.act ? G.b0 + lane : G.b0;
+    const uint32_t mi = act ? b0 + lane : b0;
     const double xi = A.x[mi], yi = A.x[n + mi], zi = A.x[2 * n + mi];
-    // box of the sinks' master positions (wave-uniform)
+    // box of the sinks' master positions (wave-uniform); the node boxes are
+    // in master coordinates too
     double blo[3], bhi[3];
     {
         const double p[3] = {xi, yi, zi};
@@ -523,7 +526,7 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
         }
     }
     const double R2sq = P.R2sq;
-    const double pad2 = A.frame[G.sys].R2pad2;
+    const double pad2 = A.frame[sys].R2pad2;
     const double eps2d = P.eps2d, R2 = P.R2d, invdR64 = P.invdR64;
 
     // Accepted pairs are summed in FP64: the neighbour sum cancels strongly
@@ -536,7 +539,7 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
     int top = 1, nr = 0, nst = 0;
     uint32_t avail = 1, tot = 0;
     if (lane == 0) {
-        S.sfirst[0] = G.sys;
+        S.sfirst[0] = sys;
         S.scnt[0] = 1;
     }
     __syncthreads();
@@ -552,7 +555,7 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
         } else {
             m0 = pair_tests<0>(S.tq + base, cnt, xi, yi, zi, R2sq);
         }
-        if (!G.act) m0 = m1 = 0;
+        if (!act) m0 = m1 = 0;
         ngb += __popcll(m0) + __popcll(m1);
         while (m0 | m1) {
             int s;
@@ -632,10 +635,12 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
         bool leaf = false, opn = false;
         uint32_t first = 0, count = 0, child = 0, nch = 0;
         if (have) {
-            const Node nd = A.node[id];
-            double D2 = dist2(gap_box(G.lo[0], G.hi[0], nd.blo[0], nd.blo[0] + nd.l),
-                              gap_box(G.lo[1], G.hi[1], nd.blo[1], nd.blo[1] + nd.l),
-                              gap_box(G.lo[2], G.hi[2], nd.blo[2], nd.blo[2] + nd.l));
+            const double *bx = A.aabb + id;
+            const int64_t nm = A.nnmax;
+            double D2 = dist2(gap_box(blo[0], bhi[0], bx[0], bx[3 * nm]),
+                              gap_box(blo[1], bhi[1], bx[nm], bx[4 * nm]),
+                              gap_box(blo[2], bhi[2], bx[2 * nm], bx[5 * nm]));
+            const Node &nd = A.node[id];
             nch = nd.meta & 255u;
             bool close = D2 < pad2;
             leaf = close && nch == 0;
@@ -670,17 +675,17 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
     }
     while (nst > 0) eval_top(nst < 128 ? nst : 128);
 
-    if (G.act) {
-        const int64_t i = G.b0 + lane;
+    if (act) {
+        const int64_t i = b0 + lane;
         ngb -= 1u;    // the sink itself
         A.acc[i] = (float)(P.Gd * hx);
         A.acc[n + i] = (float)(P.Gd * hy);
         A.acc[2 * n + i] = (float)(P.Gd * hz);
         if (A.ngb) A.ngb[i] = (int32_t)ngb;
     }
-    uint32_t ngb_sum = wave_sum(G.act ? ngb : 0u);
+    uint32_t ngb_sum = wave_sum(act ? ngb : 0u);
     if (lane == 0) {
-        atomicAdd(&A.tally[1], (unsigned long long)G.ns * cand);
+        atomicAdd(&A.tally[1], (unsigned long long)ns * cand);
         atomicAdd(&A.tally[2], (unsigned long long)ngb_sum);
     }
 }

@@ -157,6 +157,7 @@ struct BuildBufs {
     uint32_t *ptmp_k, *ptmp_v;  // [nnmax] partition scratch
     Node *node;            // [nnmax] level order
     double *S3;            // [3][nnmax] first mass moments
+    double *aabb;          // [6][nnmax] node boxes in master coordinates (lo xyz, hi xyz)
     uint32_t *lstart;      // [kMaxLevel + 2] first node of each level
     int64_t nnmax;
     // sink groups
@@ -169,6 +170,7 @@ void launch_bbox_keys(const BuildBufs &B, hipStream_t s);
 void launch_sort(BuildBufs &B, hipStream_t s);
 void launch_gather(BuildBufs &B, hipStream_t s);
 void launch_topology(BuildBufs &B, bool moments, hipStream_t s);
+void launch_levels(BuildBufs &B, bool moments, hipStream_t s);
 void launch_groups(BuildBufs &B, hipStream_t s);
 void launch_sys_of(BuildBufs &B, hipStream_t s);
 size_t scan_partials(int64_t n);
@@ -184,6 +186,8 @@ struct ForceArgs {
     const double4 *src;       // sorted build-frame positions and masses
     const double *x;          // [3][n] sorted FP64 positions (hard test)
     const float *m;           // [n] sorted masses
+    const double *aabb;       // [6][nnmax] node boxes, master coordinates
+    int64_t nnmax;
     const Frame *frame;       // [S]
     int64_t n;
     float *acc;               // [3][n] sorted order output
