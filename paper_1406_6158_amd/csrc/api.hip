@@ -213,6 +213,11 @@ void carve(Carver &C, htree_ctx *c) {
     B.node = C.take<Node>(nnmax);
     B.S3 = C.take<double>(3 * nnmax);
     B.aabb = C.take<double>(6 * nnmax);
+    {
+        int64_t m1, m2, m3;
+        refit_sizes(n, &m1, &m2, &m3);
+        B.cbox = C.take<double>(6 * (m1 + m2 + m3));
+    }
     B.lstart = C.take<uint32_t>(kMaxLevel + 2);
     B.gstart = C.take<uint32_t>(n + 1);
     B.ng = C.take<uint32_t>(4);
@@ -354,7 +359,7 @@ htree_status do_build(htree_ctx *c, bool moments) {
 // force needs a full build.
 htree_status do_refit(htree_ctx *c) {
     ev_begin(c, 0);
-    launch_levels(c->B, false, c->stream);
+    launch_refit(c->B, c->stream);
     ev_end(c, 0);
     HIP_OK(hipGetLastError());
     c->boxes = true;

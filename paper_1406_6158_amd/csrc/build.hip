@@ -648,6 +648,108 @@ __global__ __launch_bounds__(256) void k_level_pass(Node *node, const double4 *s
     }
 }
 
+// Refit after a drift (same tree, same sorted order): node boxes directly
+// from their particle ranges, which needs no level order.  Boxes of aligned
+// chunks of 32, 32^2 and 32^3 sorted particles are reduced first; a node's
+// range is then covered greedily by the largest aligned chunks that fit (at
+// most 31 pieces of each size on either side), one lane per node.  Minima
+// and maxima are exact, so the boxes equal those of the level pass.
+constexpr int kC1 = 32;
+
+// dst[6][ceil(m / 32)]: boxes of 32 consecutive entries of src (particles
+// when src6 is null: x [3][m], else boxes src6 [6][m]).
+__global__ __launch_bounds__(256) void k_box32(const double *x, const double *src6, int64_t m,
+                                               double *dst, int64_t md) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool in = i < m;
+    double lo[3], hi[3];
+    for (int a = 0; a < 3; a++) {
+        if (src6) {
+            lo[a] = in ? src6[a * m + i] : INFINITY;
+            hi[a] = in ? src6[(3 + a) * m + i] : -INFINITY;
+        } else {
+            const double v = in ? x[a * m + i] : 0.0;
+            lo[a] = in ? v : INFINITY;
+            hi[a] = in ? v : -INFINITY;
+        }
+        for (int o = 16; o > 0; o >>= 1) {     // within each half wavefront
+            lo[a] = fmin(lo[a], __shfl_xor(lo[a], o));
+            hi[a] = fmax(hi[a], __shfl_xor(hi[a], o));
+        }
+    }
+    const int64_t c = i / kC1;
+    if ((threadIdx.x & (kC1 - 1)) == 0 && c < md)
+        for (int a = 0; a < 3; a++) {
+            dst[a * md + c] = lo[a];
+            dst[(3 + a) * md + c] = hi[a];
+        }
+}
+
+__global__ __launch_bounds__(256) void k_refit(const Node *node, const uint32_t *nn_dev,
+                                               const double *x, int64_t n, const double *c1,
+                                               int64_t m1, const double *c2, int64_t m2,
+                                               const double *c3, int64_t m3, double *aabb,
+                                               int64_t nnmax) {
+    const uint32_t b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= *nn_dev) return;
+    const uint32_t f = node[b].first, e = f + node[b].count;
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    auto box = [&](const double *t, int64_t m, int64_t k) {
+        for (int a = 0; a < 3; a++) {
+            lo[a] = fmin(lo[a], t[a * m + k]);
+            hi[a] = fmax(hi[a], t[(3 + a) * m + k]);
+        }
+    };
+    constexpr uint32_t S1 = kC1, S2 = kC1 * kC1, S3 = kC1 * kC1 * kC1;
+    uint32_t i = f;
+    while (i < e) {
+        if (i % S3 == 0 && e - i >= S3) {
+            box(c3, m3, i / S3);
+            i += S3;
+        } else if (i % S2 == 0 && e - i >= S2) {
+            box(c2, m2, i / S2);
+            i += S2;
+        } else if (i % S1 == 0 && e - i >= S1) {
+            box(c1, m1, i / S1);
+            i += S1;
+        } else {
+            for (int a = 0; a < 3; a++) {
+                const double v = x[a * n + i];
+                lo[a] = fmin(lo[a], v);
+                hi[a] = fmax(hi[a], v);
+            }
+            i += 1;
+        }
+    }
+    for (int a = 0; a < 3; a++) {
+        aabb[a * nnmax + b] = lo[a];
+        aabb[(3 + a) * nnmax + b] = hi[a];
+    }
+}
+
+// Sizes of the three chunk levels for n particles (entries of 6 doubles).
+void refit_sizes(int64_t n, int64_t *m1, int64_t *m2, int64_t *m3) {
+    *m1 = (n + kC1 - 1) / kC1;
+    *m2 = (*m1 + kC1 - 1) / kC1;
+    *m3 = (*m2 + kC1 - 1) / kC1;
+}
+
+void launch_refit(BuildBufs &B, hipStream_t s) {
+    const int64_t n = B.n;
+    int64_t m1, m2, m3;
+    refit_sizes(n, &m1, &m2, &m3);
+    double *c1 = B.cbox, *c2 = c1 + 6 * m1, *c3 = c2 + 6 * m2;
+    const double *x = B.x[B.cur];
+    hipLaunchKernelGGL(k_box32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, nullptr, n,
+                       c1, m1);
+    hipLaunchKernelGGL(k_box32, dim3((unsigned)((m1 + 255) / 256)), dim3(256), 0, s, nullptr, c1,
+                       m1, c2, m2);
+    hipLaunchKernelGGL(k_box32, dim3((unsigned)((m2 + 255) / 256)), dim3(256), 0, s, nullptr, c2,
+                       m2, c3, m3);
+    hipLaunchKernelGGL(k_refit, dim3((unsigned)((B.nnmax + 255) / 256)), dim3(256), 0, s, B.node,
+                       B.nn, x, n, c1, m1, c2, m2, c3, m3, B.aabb, B.nnmax);
+}
+
 // The bottom-up pass over all levels (lstart must be current): node boxes,
 // and moments if asked.  Also the refit of the boxes after a drift.
 void launch_levels(BuildBufs &B, bool moments, hipStream_t s) {

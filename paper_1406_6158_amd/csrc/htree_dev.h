@@ -158,6 +158,7 @@ struct BuildBufs {
     Node *node;            // [nnmax] level order
     double *S3;            // [3][nnmax] first mass moments
     double *aabb;          // [6][nnmax] node boxes in master coordinates (lo xyz, hi xyz)
+    double *cbox;          // boxes of aligned 32, 32^2, 32^3-particle chunks (refit)
     uint32_t *lstart;      // [kMaxLevel + 2] first node of each level
     int64_t nnmax;
     // sink groups
@@ -171,6 +172,8 @@ void launch_sort(BuildBufs &B, hipStream_t s);
 void launch_gather(BuildBufs &B, hipStream_t s);
 void launch_topology(BuildBufs &B, bool moments, hipStream_t s);
 void launch_levels(BuildBufs &B, bool moments, hipStream_t s);
+void launch_refit(BuildBufs &B, hipStream_t s);
+void refit_sizes(int64_t n, int64_t *m1, int64_t *m2, int64_t *m3);
 void launch_groups(BuildBufs &B, hipStream_t s);
 void launch_sys_of(BuildBufs &B, hipStream_t s);
 size_t scan_partials(int64_t n);
