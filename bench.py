@@ -47,6 +47,23 @@ FLOPS_NEAR = 32
 PEAK_FP32 = 78.6
 PEAK_FP32_PACKED = 157.3
 
+# HBM bytes per launch of the soft kernel at this workload, from rocprofv3
+# FETCH_SIZE and WRITE_SIZE runs scaled by a plain-copy calibration (the
+# summary with commands is profiles/counters_plummer1m_step.txt).  Valid only
+# for the kernel source it was measured on: reported as null once force.hip or
+# htree_dev.h differ from that source.
+SOFT_TRAFFIC = {"bytes": 1018.0e6, "source_hash": "7b0ece9e978679d6"}
+
+
+def _kernel_source_hash():
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_1406_6158_amd", "csrc")
+    h = hashlib.sha256()
+    for name in ("force.hip", "htree_dev.h"):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
 
 def cpu_baseline(wl, x, m64, seconds_hint=20.0):
     """Oracle soft force (tree walk + FP64 interactions) over a sample of
@@ -439,7 +456,9 @@ def main():
                      "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32,
                      "frac_of_packed_fp32_peak": achieved / PEAK_FP32_PACKED,
-                     "traffic": None},
+                     "traffic": (SOFT_TRAFFIC["bytes"]
+                                 if _kernel_source_hash() == SOFT_TRAFFIC["source_hash"] else None),
+                     "traffic_unit": "bytes per launch (HBM, counter-measured)"},
         "cpu_baseline": None,
     }
     t.close()
