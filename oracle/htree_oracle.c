@@ -506,43 +506,23 @@ static void gpush(orc_tree *T, int64_t start)
 }
 
 /*
- * Groups of at most g sorted particles, each inside one cell: a cell with at
- * most g particles is one group; a cell with more is split into its
- * children.  Where every child of a cell holds at most g particles,
- * consecutive children (octant order) are packed into one group while the
- * total stays <= g; where some child holds more, each small child is a group
- * of its own (a run could otherwise span the big sibling's cell).  A leaf
- * with more than g particles (only possible at the deepest level, or if
- * n_crit > g) is cut into chunks of g.
+ * Groups of at most g sorted particles (reading of section III.A.2: the
+ * sinks of a group are consecutive in key order and lie in one cell).  The
+ * chunking cells are the cells with at most 16 g particles whose parent holds
+ * more (the root if it holds at most 16 g), and the leaves whose parent holds
+ * more: each is cut into consecutive chunks of g particles, the last one
+ * shorter.  A cell of at most g particles is therefore one group.
  */
+#define ORC_CHUNK_CELL 16
+
 static void groups_rec(orc_tree *T, int64_t id, int64_t g)
 {
     const onode *c = &T->nd[id];
-    if (c->count <= g) {
-        gpush(T, c->first);
-        return;
-    }
-    if (c->nchild == 0) {
+    if (c->count <= ORC_CHUNK_CELL * g || c->nchild == 0) {
         for (int64_t s = c->first; s < c->first + c->count; s += g) gpush(T, s);
         return;
     }
-    int pack = 1;
-    for (int k = 0; k < c->nchild; k++)
-        if (T->nd[c->child[k]].count > g) pack = 0;
-    int64_t run = 0;
-    for (int k = 0; k < c->nchild; k++) {
-        int64_t ck = T->nd[id].child[k];
-        const onode *ch = &T->nd[ck];
-        if (ch->count > g) {
-            groups_rec(T, ck, g);
-        } else if (!pack) {
-            gpush(T, ch->first);
-        } else {
-            if (run > 0 && run + ch->count > g) run = 0;
-            if (run == 0) gpush(T, ch->first);
-            run += ch->count;
-        }
-    }
+    for (int k = 0; k < c->nchild; k++) groups_rec(T, c->child[k], g);
 }
 
 /* Builds the sink groups for group size g; returns their number. */

@@ -221,6 +221,8 @@ void carve(Carver &C, htree_ctx *c) {
     B.lstart = C.take<uint32_t>(kMaxLevel + 2);
     B.gstart = C.take<uint32_t>(n + 1);
     B.ng = C.take<uint32_t>(4);
+    B.hgstart = C.take<uint32_t>(n + 1);
+    B.nhg = C.take<uint32_t>(4);
     c->tmp3 = C.take<float>(3 * n);
     c->pot = C.take<float>(n);
     c->ngb = C.take<int32_t>(n);
@@ -384,6 +386,8 @@ htree_status do_hard(htree_ctx *c) {
     if (!c->p.hybrid) return fail(HTREE_EINVAL, "hard_force needs hybrid mode");
     if (!c->boxes) return fail(HTREE_ESTATE, "hard_force needs a current tree");
     ForceArgs A = force_args(c);
+    A.gstart = c->B.hgstart;   // the hard kernel's own groups
+    A.ng = c->B.nhg;
     A.acc = c->B.ah[c->B.cur];
     A.ngb = c->ngb;
     ev_begin(c, 2);

@@ -803,13 +803,30 @@ void launch_topology(BuildBufs &B, bool moments, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// sink groups (the same rule as the tree contract; g is the system's group
-// size): a cell with at most g particles is a group; a bigger cell is split into its children; where all
-// children are small, consecutive children are packed while the total stays
-// <= g; a bigger leaf is cut into chunks of g.  Each node with more than g
-// particles marks the group starts among its own children; a scan turns the
-// marks into the group start table.
+// sink groups.  Soft groups (the same rule as the tree contract; g is the
+// system's group size): the chunking cells -- cells of at most 16 g particles
+// whose parent holds more (the root if it is that small), and leaves whose
+// parent holds more -- are cut into consecutive chunks of g.  Hard groups
+// (the hard kernel's own table; any partition gives the same neighbour sets):
+// a cell with at most g particles is a group; a bigger cell is split into its
+// children; where all children are small, consecutive children are packed
+// while the total stays <= g; a bigger leaf is cut into chunks of g.  Each
+// node marks the group starts it owns; a scan turns the marks into a table.
 // ---------------------------------------------------------------------------
+constexpr uint32_t kChunkCell = 16;
+
+__global__ __launch_bounds__(256) void k_soft_group_marks(const Node *node, const uint32_t *nn_dev,
+                                                          const Sys *sys, uint32_t *flag) {
+    uint32_t b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= *nn_dev) return;
+    const Node &N = node[b];
+    const uint32_t g = sys[N.sys].g, lim = kChunkCell * g;
+    const uint32_t count = N.count, nch = N.meta & 255u;
+    if (count > lim && nch != 0) return;                        // split further
+    if ((N.meta >> 8) != 0 && node[N.parent].count <= lim) return;   // inside a chunking cell
+    for (uint32_t s = 0; s < count; s += g) flag[N.first + s] = 1u;
+}
+
 __global__ __launch_bounds__(256) void k_group_marks(const Node *node, const uint32_t *nn_dev,
                                                      const Sys *sys, uint32_t *flag) {
     uint32_t b = blockIdx.x * 256 + threadIdx.x;
@@ -852,13 +869,20 @@ __global__ __launch_bounds__(256) void k_group_compact(const uint32_t *scan, int
 
 void launch_groups(BuildBufs &B, hipStream_t s) {
     int64_t n = B.n;
-    uint32_t *flag = B.nstart;    // free once the topology is built
-    launch_zero_u32(flag, n + 1, s);
     unsigned gn = (unsigned)((B.nnmax + 255) / 256);
-    hipLaunchKernelGGL(k_group_marks, dim3(gn), dim3(256), 0, s, B.node, B.nn, B.sys, flag);
+    unsigned gp = (unsigned)((n + 255) / 256);
+    // soft groups; the flags live in nstart, free once the topology is built
+    uint32_t *flag = B.nstart;
+    launch_zero_u32(flag, n + 1, s);
+    hipLaunchKernelGGL(k_soft_group_marks, dim3(gn), dim3(256), 0, s, B.node, B.nn, B.sys, flag);
     launch_scan_u32(flag, n + 1, B.scan_part, B.ng, s);
-    hipLaunchKernelGGL(k_group_compact, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, flag, n,
-                       B.gstart);
+    hipLaunchKernelGGL(k_group_compact, dim3(gp), dim3(256), 0, s, flag, n, B.gstart);
+    // hard groups; flags in pre_key (nnmax >= n + 1 entries, free after the build)
+    uint32_t *hflag = B.pre_key;
+    launch_zero_u32(hflag, n + 1, s);
+    hipLaunchKernelGGL(k_group_marks, dim3(gn), dim3(256), 0, s, B.node, B.nn, B.sys, hflag);
+    launch_scan_u32(hflag, n + 1, B.scan_part, B.nhg, s);
+    hipLaunchKernelGGL(k_group_compact, dim3(gp), dim3(256), 0, s, hflag, n, B.hgstart);
 }
 
 }  // namespace htree

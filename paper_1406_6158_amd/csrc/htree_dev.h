@@ -162,8 +162,10 @@ struct BuildBufs {
     uint32_t *lstart;      // [kMaxLevel + 2] first node of each level
     int64_t nnmax;
     // sink groups
-    uint32_t *gstart;      // [n+1] group start positions (ng + 1 used)
-    uint32_t *ng;          // device group count
+    uint32_t *gstart;      // [n+1] soft group start positions (ng + 1 used)
+    uint32_t *ng;          // device soft group count
+    uint32_t *hgstart;     // [n+1] hard group start positions (nhg + 1 used)
+    uint32_t *nhg;         // device hard group count
 };
 
 // Host launch wrappers (build.hip).

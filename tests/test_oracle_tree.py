@@ -250,50 +250,42 @@ def test_tree_force_error_reported(orc):
 
 
 @pytest.mark.parametrize("n,g,n_crit,seed", [(1, 64, 16, 1), (64, 64, 16, 2), (65, 64, 16, 3),
+                                             (1024, 64, 16, 7), (1025, 64, 16, 8),
                                              (20000, 64, 16, 4), (5000, 32, 8, 5),
                                              (3000, 16, 64, 6)])
 def test_sink_groups(orc, n, g, n_crit, seed):
-    """Groups partition the sorted particles, hold at most g each, and each is a
-    whole cell, a run of consecutive sibling cells of one parent, or a g-chunk
-    of an oversized leaf; consecutive sibling runs could not have been merged."""
+    """Groups are the g-chunks of the chunking cells: the maximal cells with
+    at most 16 g particles and the leaves whose parent holds more.  The
+    expected starts are built from the node list by brute force; the
+    partition, the size bound and the single-cell property are checked too."""
     x, v, m = synth.plummer(n, seed)
     if n > 1000:
         x[:, 500:700] = x[:, 499:500]          # oversized deepest-level leaf
     T = orc.Tree(x, m, n_crit=n_crit, group=g)
     st = T.group_starts()
     assert st[0] == 0 and st[-1] == n and np.all(np.diff(st) > 0)
-    cnt = np.diff(st)
-    assert np.all(cnt <= g)
+    assert np.all(np.diff(st) <= g)
     nd = T.nodes()
-    first, count, parent = nd["first"], nd["count"], nd["parent"]
-    end = first + count
-    kinds = []
-    for b, e in zip(st[:-1], st[1:]):
-        # smallest node containing [b, e)
-        inside = np.nonzero((first <= b) & (end >= e))[0]
-        c = inside[np.argmax(nd["level"][inside])]
-        if first[c] == b and end[c] == e:
-            assert count[c] <= g or nd["nchild"][c] == 0
-            kinds.append(("cell", c))
-            continue
-        if nd["nchild"][c] == 0:                    # chunk of an oversized leaf
-            assert count[c] > g and (b - first[c]) % g == 0
-            kinds.append(("chunk", c))
-            continue
-        ch = np.nonzero(parent == c)[0]
-        sel = ch[(first[ch] >= b) & (end[ch] <= e)]
-        assert first[sel].min() == b and end[sel].max() == e       # whole children
-        assert np.all(count[sel] <= g) and count[sel].sum() == e - b
-        assert count[c] > g
-        kinds.append(("run", c, sel))
-    # packing is greedy: a run followed by a run of the same parent could not
-    # have absorbed that run's first child
-    for k in range(len(kinds) - 1):
-        a, b2 = kinds[k], kinds[k + 1]
-        if a[0] == "run" and b2[0] == "run" and a[1] == b2[1]:
-            nxt = b2[2][np.argmin(first[b2[2]])]
-            if first[nxt] == st[k + 1]:
-                assert cnt[k] + count[nxt] > g
+    first, count, parent, nch = nd["first"], nd["count"], nd["parent"], nd["nchild"]
+    lim = 16 * g
+    small = (count <= lim) | (nch == 0)
+    is_root = (parent < 0) | (parent == np.arange(len(parent)))
+    chunking = small & (is_root | (count[np.maximum(parent, 0)] > lim))
+    # chunking cells tile the particles
+    cf, cc = first[chunking], count[chunking]
+    order = np.argsort(cf)
+    assert cf[order][0] == 0 and np.all(cf[order][1:] == (cf + cc)[order][:-1])
+    assert (cf + cc)[order][-1] == n
+    want = np.sort(np.concatenate([np.arange(f, f + c, g) for f, c in zip(cf, cc)]))
+    assert np.array_equal(st[:-1], want)
+    # a group never straddles two chunking cells
+    end_c = np.repeat(cf + cc, (cc + g - 1) // g)[np.argsort(np.concatenate(
+        [np.arange(f, f + c, g) for f, c in zip(cf, cc)]))]
+    assert np.all(st[1:] <= end_c)
+    if n >= 20000:
+        # the oversized deepest-level leaf is cut into chunks of g
+        leaf = np.nonzero((nch == 0) & (count > g))[0]
+        assert len(leaf) > 0
 
 
 def test_groups_are_compact(orc):
