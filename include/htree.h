@@ -65,7 +65,9 @@ typedef struct {
     int32_t n_crit;       /* a cell splits while it holds >= n_crit particles (>= 1) */
     int32_t group_size;   /* at most this many sinks share one walk, 1..64 (64: one  */
                           /* sink per lane of a wavefront)                          */
-    int32_t precision;    /* 0: FP32 interactions with compensated tile sums         */
+    int32_t precision;    /* soft interactions: 0 FP32 with compensated tile sums;   */
+                          /* 1 FP64 (results are still stored as FP32); the hard    */
+                          /* force always sums its pair terms in FP64               */
     int32_t flags;        /* HTREE_F_*                                               */
 } htree_params;
 

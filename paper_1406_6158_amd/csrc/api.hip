@@ -67,7 +67,8 @@ htree_status validate_one(const htree_params *p, int64_t n) {
     if (p->n_crit < 1 || p->n_crit > 4096) return fail(HTREE_EINVAL, "n_crit must be in [1, 4096]");
     if (p->group_size < 1 || p->group_size > 64)
         return fail(HTREE_EINVAL, "group_size must be in [1, 64]");
-    if (p->precision != 0) return fail(HTREE_EINVAL, "precision must be 0 (FP32 interactions)");
+    if (p->precision != 0 && p->precision != 1)
+        return fail(HTREE_EINVAL, "precision must be 0 (FP32) or 1 (FP64 interactions)");
     if (p->flags & ~(HTREE_F_POT | HTREE_F_TIMING)) return fail(HTREE_EINVAL, "unknown flags");
     return HTREE_OK;
 }
@@ -375,7 +376,7 @@ htree_status do_soft(htree_ctx *c) {
     const bool pot = (c->p.flags & HTREE_F_POT) != 0;
     A.pot = pot ? c->pot : nullptr;
     ev_begin(c, 1);
-    launch_soft(A, c->p.hybrid != 0, pot, c->n_wg, c->stream);
+    launch_soft(A, c->p.hybrid != 0, pot, c->p.precision, c->n_wg, c->stream);
     ev_end(c, 1);
     HIP_OK(hipGetLastError());
     c->have_soft = true;

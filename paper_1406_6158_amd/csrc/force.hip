@@ -45,12 +45,32 @@ constexpr int kRQ = 128;
 __device__ inline float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 
-__device__ inline void kahan(float &s, float &c, float v) {
-    float y = v - c;
-    float t = s + y;
-    c = (t - s) - y;
-    s = t;
+// Arithmetic of the soft interactions: FP32 (precision 0) or FP64
+// (precision 1).  Sources are staged as offsets from the group centre in that
+// type, with the mass.
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+template <typename T> using vec4_t = typename Vec4<T>::type;
+
+__device__ inline float4 make_vec4(float a, float b, float c, float d) { return make_float4(a, b, c, d); }
+__device__ inline double4 make_vec4(double a, double b, double c, double d) {
+    return make_double4(a, b, c, d);
 }
+
+// 1/sqrt: the hardware FP32 estimate, or in FP64 from that seed with two
+// Newton steps (relative error near the FP64 rounding).
+__device__ inline float rsqrt_t(float x) { return rsq(x); }
+__device__ inline double rsqrt_t(double x) {
+    double y = (double)rsq((float)x);
+    y = y * fma(-0.5 * x, y * y, 1.5);
+    return y * fma(-0.5 * x, y * y, 1.5);
+}
+__device__ inline float sqrt_t(float x) { return fsqrt(x); }
+__device__ inline double sqrt_t(double x) { return x > 0.0 ? x * rsqrt_t(x) : 0.0; }
+__device__ inline float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ inline double fma_t(double a, double b, double c) { return fma(a, b, c); }
+
 
 __device__ inline double gap_pt(double lo, double hi, double p) {
     double g = fmax(lo - p, p - hi);
@@ -66,11 +86,12 @@ __device__ inline double dist2(double gx, double gy, double gz) {
 
 // 1 - K(r) as a polynomial in w = 1 - Y^2 (K(Y) = S(Y^2) with the quintic
 // S(s) = 10 s^3 - 15 s^4 + 6 s^5, and 1 - S(s) = S(1 - s)).
-__device__ inline float one_minus_K(float r, float R2f, float invdR) {
-    float Y = (R2f - r) * invdR;
-    Y = fminf(fmaxf(Y, 0.0f), 1.0f);
-    float w = fmaf(-Y, Y, 1.0f);
-    float t = fmaf(fmaf(6.0f, w, -15.0f), w, 10.0f);
+template <typename T>
+__device__ inline T one_minus_K(T r, T R2, T invdR) {
+    T Y = (R2 - r) * invdR;
+    Y = Y < (T)0 ? (T)0 : (Y > (T)1 ? (T)1 : Y);
+    T w = fma_t(-Y, Y, (T)1);
+    T t = fma_t(fma_t((T)6, w, (T)-15), w, (T)10);
     return t * (w * w * w);
 }
 
@@ -136,36 +157,44 @@ __device__ inline void group_setup(const double4 *src, const uint32_t *gstart,
     }
 }
 
-// A source particle as an FP32 offset from the group centre, with its mass.
-__device__ inline float4 rel_src(const double4 &q, const GroupCtx &G) {
-    return make_float4((float)(q.x - G.c[0]), (float)(q.y - G.c[1]), (float)(q.z - G.c[2]),
-                       (float)q.w);
+// A source particle as an offset from the group centre, with its mass.
+template <typename T>
+__device__ inline vec4_t<T> rel_src(const double4 &q, const GroupCtx &G) {
+    return make_vec4((T)(q.x - G.c[0]), (T)(q.y - G.c[1]), (T)(q.z - G.c[2]), (T)q.w);
 }
 
 // ---------------------------------------------------------------------------
 // interaction loops
 // ---------------------------------------------------------------------------
+template <typename T>
 struct Acc {
-    float a[3], c[3];   // running sums and Kahan compensations
-    float p, pc;
+    T a[3], c[3];   // running sums and Kahan compensations
+    T p, pc;
 };
 
-template <bool POT, int CNT>
-__device__ inline void eval_far(const float4 *t, int cnt, float sx, float sy, float sz, float eps2,
-                                Acc &A) {
-    float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
+template <typename T>
+__device__ inline void kahan(T &s, T &c, T v) {
+    T y = v - c;
+    T t = s + y;
+    c = (t - s) - y;
+    s = t;
+}
+
+template <bool POT, int CNT, typename T>
+__device__ inline void eval_far(const vec4_t<T> *t, int cnt, T sx, T sy, T sz, T eps2, Acc<T> &A) {
+    T ax = 0, ay = 0, az = 0, ph = 0;
     const int nloop = CNT > 0 ? CNT : cnt;
 #pragma unroll 8
     for (int j = 0; j < nloop; j++) {
-        float4 q = t[j];
-        float dx = q.x - sx, dy = q.y - sy, dz = q.z - sz;
-        float r2 = fmaf(dz, dz, fmaf(dy, dy, fmaf(dx, dx, eps2)));
-        float ri = rsq(r2);
-        float mr = q.w * ri;
-        float f = mr * (ri * ri);
-        ax = fmaf(f, dx, ax);
-        ay = fmaf(f, dy, ay);
-        az = fmaf(f, dz, az);
+        const vec4_t<T> q = t[j];
+        T dx = q.x - sx, dy = q.y - sy, dz = q.z - sz;
+        T r2 = fma_t(dz, dz, fma_t(dy, dy, fma_t(dx, dx, eps2)));
+        T ri = rsqrt_t(r2);
+        T mr = q.w * ri;
+        T f = mr * (ri * ri);
+        ax = fma_t(f, dx, ax);
+        ay = fma_t(f, dy, ay);
+        az = fma_t(f, dz, az);
         if (POT) ph -= mr;
     }
     kahan(A.a[0], A.c[0], ax);
@@ -174,22 +203,22 @@ __device__ inline void eval_far(const float4 *t, int cnt, float sx, float sy, fl
     if (POT) kahan(A.p, A.pc, ph);
 }
 
-template <bool POT>
-__device__ inline void eval_near(const float4 *t, int cnt, float sx, float sy, float sz,
-                                 float eps2, float R2f, float invdR, Acc &A) {
-    float ax = 0.f, ay = 0.f, az = 0.f, ph = 0.f;
+template <bool POT, typename T>
+__device__ inline void eval_near(const vec4_t<T> *t, int cnt, T sx, T sy, T sz, T eps2, T R2,
+                                 T invdR, Acc<T> &A) {
+    T ax = 0, ay = 0, az = 0, ph = 0;
 #pragma unroll 4
     for (int j = 0; j < cnt; j++) {
-        float4 q = t[j];
-        float dx = q.x - sx, dy = q.y - sy, dz = q.z - sz;
-        float u2 = fmaf(dz, dz, fmaf(dy, dy, dx * dx));
-        float ri = rsq(u2 + eps2);
-        float mr = q.w * ri;
-        float w = one_minus_K(fsqrt(u2), R2f, invdR);
-        float f = mr * (ri * ri) * w;
-        ax = fmaf(f, dx, ax);
-        ay = fmaf(f, dy, ay);
-        az = fmaf(f, dz, az);
+        const vec4_t<T> q = t[j];
+        T dx = q.x - sx, dy = q.y - sy, dz = q.z - sz;
+        T u2 = fma_t(dz, dz, fma_t(dy, dy, dx * dx));
+        T ri = rsqrt_t(u2 + eps2);
+        T mr = q.w * ri;
+        T w = one_minus_K(sqrt_t(u2), R2, invdR);
+        T f = mr * (ri * ri) * w;
+        ax = fma_t(f, dx, ax);
+        ay = fma_t(f, dy, ay);
+        az = fma_t(f, dz, az);
         if (POT) ph -= mr;
     }
     kahan(A.a[0], A.c[0], ax);
@@ -245,30 +274,45 @@ __device__ inline int step_width(int top, uint32_t avail) {
 // ---------------------------------------------------------------------------
 // soft force
 // ---------------------------------------------------------------------------
+template <typename T>
 struct SoftLDS {
     uint32_t sfirst[kStk], scnt[kStk];
-    float4 pc[kPC];
-    float4 tile[2][64];
+    vec4_t<T> pc[kPC];
+    vec4_t<T> tile[2][64];
     uint32_t ffirst[kRQ], fcnt[kRQ];
     uint32_t nfirst[kRQ], ncnt[kRQ];
     uint32_t scan[64];
 };
 
-template <bool HYBRID, bool POT>
-__device__ void soft_group(const ForceArgs &A, SoftLDS &S, uint32_t grp) {
+// Per-system constants of the interactions in the arithmetic type.
+struct SoftConst32 {
+    float eps2, R2, invdR, G;
+    __device__ SoftConst32(const SysF &P) : eps2(P.eps2), R2(P.R2f), invdR(P.invdR), G(P.G) {}
+};
+struct SoftConst64 {
+    double eps2, R2, invdR, G;
+    __device__ SoftConst64(const SysF &P) : eps2(P.eps2d), R2(P.R2d), invdR(P.invdR64), G(P.Gd) {}
+};
+template <typename T> struct SoftConst;
+template <> struct SoftConst<float> : SoftConst32 { using SoftConst32::SoftConst32; };
+template <> struct SoftConst<double> : SoftConst64 { using SoftConst64::SoftConst64; };
+
+template <bool HYBRID, bool POT, typename T>
+__device__ void soft_group(const ForceArgs &A, SoftLDS<T> &S, uint32_t grp) {
     const int lane = __lane_id();
     const uint64_t lt = lanemask_lt();
     GroupCtx G;
     double4 me;
     group_setup(A.src, A.gstart, A.sys_of, grp, G, me);
     const SysF P = A.sysf[G.sys];
-    const float sx = (float)(me.x - G.c[0]);
-    const float sy = (float)(me.y - G.c[1]);
-    const float sz = (float)(me.z - G.c[2]);
+    const SoftConst<T> Q(P);
+    const T sx = (T)(me.x - G.c[0]);
+    const T sy = (T)(me.y - G.c[1]);
+    const T sz = (T)(me.z - G.c[2]);
     const double R2sq = P.R2sq;
-    const float eps2 = P.eps2;
+    const T eps2 = Q.eps2;
 
-    Acc acc = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}, 0.f, 0.f};
+    Acc<T> acc = {{0, 0, 0}, {0, 0, 0}, 0, 0};
     uint32_t n_pc = 0, n_far = 0, n_near = 0;
     int top = 1, npc = 0, nfr = 0, nnr = 0;
     uint32_t avail = 1, ftot = 0, ntot = 0;
@@ -286,7 +330,7 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS &S, uint32_t grp) {
 
         bool acc_c = false, leaf = false, opn = false, nr = false;
         uint32_t first = 0, count = 0, child = 0, nch = 0;
-        float4 pcs = make_float4(0.f, 0.f, 0.f, 0.f);
+        vec4_t<T> pcs = make_vec4((T)0, (T)0, (T)0, (T)0);
         if (have) {
             const Node nd = A.node[id];
             double D1 = dist2(gap_pt(G.lo[0], G.hi[0], nd.com[0]),
@@ -305,8 +349,8 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS &S, uint32_t grp) {
             count = nd.count;
             child = nd.child;
             if (acc_c)
-                pcs = make_float4((float)(nd.com[0] - G.c[0]), (float)(nd.com[1] - G.c[1]),
-                                  (float)(nd.com[2] - G.c[2]), (float)nd.M);
+                pcs = make_vec4((T)(nd.com[0] - G.c[0]), (T)(nd.com[1] - G.c[1]),
+                                (T)(nd.com[2] - G.c[2]), (T)nd.M);
         }
         // accepted cells -> particle-cell sources
         uint64_t m = __ballot(acc_c);
@@ -350,7 +394,7 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS &S, uint32_t grp) {
         __syncthreads();
 
         while (npc >= 64) {
-            eval_far<POT, 64>(S.pc + (npc - 64), 64, sx, sy, sz, eps2, acc);
+            eval_far<POT, 64, T>(S.pc + (npc - 64), 64, sx, sy, sz, eps2, acc);
             npc -= 64;
         }
         // full particle tiles, double-buffered: the gather of the next tile
@@ -360,14 +404,14 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS &S, uint32_t grp) {
             ftot -= 64;
             int buf = 0;
             for (;;) {
-                S.tile[buf][lane] = rel_src(q, G);
+                S.tile[buf][lane] = rel_src<T>(q, G);
                 __syncthreads();
                 const bool more = ftot >= 64;
                 if (more) {
                     q = A.src[take_items(S.ffirst, S.fcnt, nfr, 64, S.scan)];
                     ftot -= 64;
                 }
-                eval_far<POT, 64>(S.tile[buf], 64, sx, sy, sz, eps2, acc);
+                eval_far<POT, 64, T>(S.tile[buf], 64, sx, sy, sz, eps2, acc);
                 if (!more) break;
                 buf ^= 1;
             }
@@ -378,14 +422,14 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS &S, uint32_t grp) {
             ntot -= 64;
             int buf = 0;
             for (;;) {
-                S.tile[buf][lane] = rel_src(q, G);
+                S.tile[buf][lane] = rel_src<T>(q, G);
                 __syncthreads();
                 const bool more = ntot >= 64;
                 if (more) {
                     q = A.src[take_items(S.nfirst, S.ncnt, nnr, 64, S.scan)];
                     ntot -= 64;
                 }
-                eval_near<POT>(S.tile[buf], 64, sx, sy, sz, eps2, P.R2f, P.invdR, acc);
+                eval_near<POT, T>(S.tile[buf], 64, sx, sy, sz, eps2, Q.R2, Q.invdR, acc);
                 if (!more) break;
                 buf ^= 1;
             }
@@ -393,34 +437,34 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS &S, uint32_t grp) {
         }
     }
     // partial tiles
-    if (npc > 0) eval_far<POT, 0>(S.pc, npc, sx, sy, sz, eps2, acc);
+    if (npc > 0) eval_far<POT, 0, T>(S.pc, npc, sx, sy, sz, eps2, acc);
     if (ftot > 0) {
         int want = (int)ftot;
         uint32_t pi = take_items(S.ffirst, S.fcnt, nfr, want, S.scan);
-        if (lane < want) S.tile[0][lane] = rel_src(A.src[pi], G);
+        if (lane < want) S.tile[0][lane] = rel_src<T>(A.src[pi], G);
         __syncthreads();
-        eval_far<POT, 0>(S.tile[0], want, sx, sy, sz, eps2, acc);
+        eval_far<POT, 0, T>(S.tile[0], want, sx, sy, sz, eps2, acc);
         __syncthreads();
     }
     if (HYBRID && ntot > 0) {
         int want = (int)ntot;
         uint32_t pi = take_items(S.nfirst, S.ncnt, nnr, want, S.scan);
-        if (lane < want) S.tile[0][lane] = rel_src(A.src[pi], G);
+        if (lane < want) S.tile[0][lane] = rel_src<T>(A.src[pi], G);
         __syncthreads();
-        eval_near<POT>(S.tile[0], want, sx, sy, sz, eps2, P.R2f, P.invdR, acc);
+        eval_near<POT, T>(S.tile[0], want, sx, sy, sz, eps2, Q.R2, Q.invdR, acc);
         __syncthreads();
     }
 
     if (G.act) {
         const int64_t i = G.b0 + lane;
         const int64_t n = A.n;
-        A.acc[i] = P.G * (acc.a[0] - acc.c[0]);
-        A.acc[n + i] = P.G * (acc.a[1] - acc.c[1]);
-        A.acc[2 * n + i] = P.G * (acc.a[2] - acc.c[2]);
+        A.acc[i] = (float)(Q.G * (acc.a[0] - acc.c[0]));
+        A.acc[n + i] = (float)(Q.G * (acc.a[1] - acc.c[1]));
+        A.acc[2 * n + i] = (float)(Q.G * (acc.a[2] - acc.c[2]));
         if (POT) {
             // the sink itself was summed once among its own leaf's particles
-            kahan(acc.p, acc.pc, (float)me.w * rsq(eps2));
-            A.pot[i] = P.G * (acc.p - acc.pc);
+            kahan(acc.p, acc.pc, (T)me.w * rsqrt_t(eps2));
+            A.pot[i] = (float)(Q.G * (acc.p - acc.pc));
         }
     }
     if (lane == 0) {
@@ -434,28 +478,36 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS &S, uint32_t grp) {
     }
 }
 
-template <bool HYBRID, bool POT>
+template <bool HYBRID, bool POT, typename T>
 __global__ __launch_bounds__(64) void k_soft(ForceArgs A) {
-    __shared__ SoftLDS S;
+    __shared__ SoftLDS<T> S;
     const uint32_t ng = *A.ng;
     for (uint32_t idx = blockIdx.x; idx < ng; idx += gridDim.x) {
         const uint32_t grp = sched_group(idx, ng);
         HT_CHECK(grp < ng);
         HT_CHECK(A.gstart[grp + 1] > A.gstart[grp] && A.gstart[grp + 1] - A.gstart[grp] <= 64);
-        soft_group<HYBRID, POT>(A, S, grp);
+        soft_group<HYBRID, POT, T>(A, S, grp);
     }
 }
 
-void launch_soft(const ForceArgs &A, bool hybrid, bool pot, int n_wg, hipStream_t s) {
-    HT_CHECK(n_wg > 0 && n_wg % 8 == 0);
-    dim3 grid((unsigned)n_wg), block(64);
+template <typename T>
+void launch_soft_t(const ForceArgs &A, bool hybrid, bool pot, dim3 grid, hipStream_t s) {
+    dim3 block(64);
     if (hybrid) {
-        if (pot) hipLaunchKernelGGL((k_soft<true, true>), grid, block, 0, s, A);
-        else hipLaunchKernelGGL((k_soft<true, false>), grid, block, 0, s, A);
+        if (pot) hipLaunchKernelGGL((k_soft<true, true, T>), grid, block, 0, s, A);
+        else hipLaunchKernelGGL((k_soft<true, false, T>), grid, block, 0, s, A);
     } else {
-        if (pot) hipLaunchKernelGGL((k_soft<false, true>), grid, block, 0, s, A);
-        else hipLaunchKernelGGL((k_soft<false, false>), grid, block, 0, s, A);
+        if (pot) hipLaunchKernelGGL((k_soft<false, true, T>), grid, block, 0, s, A);
+        else hipLaunchKernelGGL((k_soft<false, false, T>), grid, block, 0, s, A);
     }
+}
+
+void launch_soft(const ForceArgs &A, bool hybrid, bool pot, int precision, int n_wg,
+                 hipStream_t s) {
+    HT_CHECK(n_wg > 0 && n_wg % 8 == 0);
+    const dim3 grid((unsigned)n_wg);
+    if (precision == 1) launch_soft_t<double>(A, hybrid, pot, grid, s);
+    else launch_soft_t<float>(A, hybrid, pot, grid, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -202,7 +202,8 @@ struct ForceArgs {
     unsigned long long *tally;  // [4] interaction tallies
     uint32_t *status;
 };
-void launch_soft(const ForceArgs &A, bool hybrid, bool pot, int n_wg, hipStream_t s);
+void launch_soft(const ForceArgs &A, bool hybrid, bool pot, int precision, int n_wg,
+                 hipStream_t s);
 void launch_hard(const ForceArgs &A, int n_wg, hipStream_t s);
 
 // Integrator and layout kernels (integrate.hip).

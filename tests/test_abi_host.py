@@ -111,3 +111,8 @@ def test_batch_workspace_and_validation(abi):
     bad = [abi.default_params(), abi.default_params(eps=-1.0)]
     assert abi.batch_workspace_bytes(bad, [10, 10]) == 0
     assert abi.batch_workspace_bytes(ps[:2], [10, 0]) == 0
+
+
+def test_precision_fp64_accepted(abi):
+    p = abi.default_params(precision=1)
+    assert abi.workspace_bytes(p, 1000) > 0

@@ -129,3 +129,25 @@ def test_call_order_errors():
     with pytest.raises(P.HTreeError) as ei:
         tp.hard_force()
     assert ei.value.code == P.HTREE_EINVAL
+
+
+@pytest.mark.parametrize("name", ["plummer4k", "cube5000"])
+@pytest.mark.parametrize("hybrid", [0, 1])
+def test_soft_force_fp64(orc, name, hybrid):
+    """precision = 1: FP64 interactions; only the FP32 rounding of the stored
+    acceleration and potential (2^-24 relative per component) remains."""
+    torch, P = need_gpu()
+    (x, v, m), eps, R1, R2 = _wl(name)
+    x, v32, m32, v64, m64 = as_inputs(x, v, m)
+    t = make_tree(P, torch, x, v32, m32, eps=eps, theta=0.5, R1=R1, R2=R2, hybrid=hybrid,
+                  precision=1, flags=P.F_POT)
+    t.build_tree()
+    a, pot = t.soft_force(want_pot=True)
+    t.sync()
+    T = orc.Tree(x, m64, n_crit=16, theta=0.5)
+    oa, opot, _ = T.soft(1.0, eps, R1, R2, hybrid, potential=True)
+    e = rel_err(a.cpu().numpy().astype(np.float64), oa)
+    report("fp64 soft %s hybrid %d" % (name, hybrid), e)
+    assert e.max() <= 1e-7
+    ep = np.abs(pot.cpu().numpy() - opot) / np.abs(opot)
+    assert ep.max() <= 1e-7

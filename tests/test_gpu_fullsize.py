@@ -11,13 +11,13 @@ from tests._gpu import as_inputs, make_tree, need_gpu, rel_err, report
 pytestmark = pytest.mark.gpu
 
 
-def _check(orc, torch, P, wl, theta, n_groups_sample, n_sink_sample, full_counts):
+def _check(orc, torch, P, wl, theta, n_groups_sample, n_sink_sample, full_counts, precision=0):
     x, v, m = wl.make()
     x, v32, m32, v64, m64 = as_inputs(x, v, m)
     n = x.shape[1]
-    print(wl.name, "theta", theta, "n", n, flush=True)
+    print(wl.name, "theta", theta, "n", n, "precision", precision, flush=True)
     t = make_tree(P, torch, x, v32, m32, eps=wl.eps, theta=theta, R1=wl.R1, R2=wl.R2,
-                  n_crit=wl.n_crit)
+                  n_crit=wl.n_crit, precision=precision)
     t.build_tree()
     a_s = t.soft_force()
     a_h, ngb = t.hard_force()
@@ -47,7 +47,9 @@ def _check(orc, torch, P, wl, theta, n_groups_sample, n_sink_sample, full_counts
     sinks = np.concatenate([operm[gst[k]:gst[k + 1]] for k in groups])
     e = rel_err(a_s.cpu().numpy()[:, sinks].astype(np.float64), oacc[:, sinks])
     report("soft sampled groups", e)
-    assert np.percentile(e, 99) <= 1e-5
+    # FP32 interactions: the stated 1e-5; FP64 interactions: only the FP32
+    # rounding of the stored result remains (2^-24 per component)
+    assert np.percentile(e, 99) <= (1e-5 if precision == 0 else 1e-7)
     hs = synth.sample_indices(n, n_sink_sample, wl.sample_seed + 1)
     oah, _, ongb = orc.split_direct(x, m64, 1.0, wl.eps, wl.R1, wl.R2, sinks=hs, soft=False)
     assert np.array_equal(ngb.cpu().numpy()[hs].astype(np.int64), ongb)
@@ -67,3 +69,9 @@ def test_plummer_2e20(orc):
 def test_hernquist_2e23(orc, theta):
     torch, P = need_gpu()
     _check(orc, torch, P, synth.WORKLOADS["hernquist8m"], theta, 32, 512, False)
+
+
+def test_hernquist_2e23_fp64(orc):
+    # the same halo at theta = 0.6 with FP64 interactions (precision 1)
+    torch, P = need_gpu()
+    _check(orc, torch, P, synth.WORKLOADS["hernquist8m"], 0.6, 32, 512, False, precision=1)
