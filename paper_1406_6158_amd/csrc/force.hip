@@ -70,6 +70,8 @@ __device__ inline float sqrt_t(float x) { return fsqrt(x); }
 __device__ inline double sqrt_t(double x) { return x > 0.0 ? x * rsqrt_t(x) : 0.0; }
 __device__ inline float fma_t(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ inline double fma_t(double a, double b, double c) { return fma(a, b, c); }
+__device__ inline float clamp01(float y) { return fminf(fmaxf(y, 0.0f), 1.0f); }
+__device__ inline double clamp01(double y) { return fmin(fmax(y, 0.0), 1.0); }
 
 
 __device__ inline double gap_pt(double lo, double hi, double p) {
@@ -88,8 +90,7 @@ __device__ inline double dist2(double gx, double gy, double gz) {
 // S(s) = 10 s^3 - 15 s^4 + 6 s^5, and 1 - S(s) = S(1 - s)).
 template <typename T>
 __device__ inline T one_minus_K(T r, T R2, T invdR) {
-    T Y = (R2 - r) * invdR;
-    Y = Y < (T)0 ? (T)0 : (Y > (T)1 ? (T)1 : Y);
+    const T Y = clamp01((R2 - r) * invdR);
     T w = fma_t(-Y, Y, (T)1);
     T t = fma_t(fma_t((T)6, w, (T)-15), w, (T)10);
     return t * (w * w * w);
