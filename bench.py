@@ -52,16 +52,21 @@ PEAK_FP32_PACKED = 157.3
 # summary with commands is profiles/counters_plummer1m_step.txt).  Valid only
 # for the kernel source it was measured on: reported as null once force.hip or
 # htree_dev.h differ from that source.
-SOFT_TRAFFIC = {"bytes": 1440.5e6, "source_hash": "6b0123a9003cba49"}
+SOFT_TRAFFIC = {"bytes": 1440.5e6, "source_hash": "acbf69b4a0b95eb8"}
 
 
 def _kernel_source_hash():
+    """Hash of the soft kernel's sources with comments and blank lines
+    dropped (comment edits do not change the kernel)."""
     import hashlib
     csrc = os.path.join(ROOT, "paper_1406_6158_amd", "csrc")
     h = hashlib.sha256()
     for name in ("force.hip", "htree_dev.h"):
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(csrc, name)) as f:
+            for line in f:
+                code = line.split("//", 1)[0].strip()
+                if code:
+                    h.update(code.encode() + b"\n")
     return h.hexdigest()[:16]
 
 

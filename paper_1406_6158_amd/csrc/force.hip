@@ -1,8 +1,8 @@
 // force.hip -- soft (tree) and hard (neighbour) force kernels for gfx950.
 //
 // Soft force (section II.B walk, grouped sinks of section III.A.2, split of
-// section II.C).  One wavefront serves one sink group (at most 64 sinks that
-// share a tree cell), one sink per lane.  The walk is wide depth-first over a
+// section II.C).  One wavefront serves one sink group (at most 64 sinks,
+// consecutive in key order inside one cell), one sink per lane.  The walk is wide depth-first over a
 // stack of child ranges (first node, count) in LDS: each step takes up to 64
 // nodes from the top ranges, one per lane, and tests them in FP64 against the
 // group's bounding box:
@@ -11,9 +11,9 @@
 // Accepted cells become particle-cell sources, rejected leaves particle
 // sources ("near", weighted by 1 - K, iff hybrid and D2 < R2^2), other nodes
 // push the range of their (contiguous) children.  Sources are staged in LDS as
-// FP32 offsets from the group centre plus mass; every 64 of them all lanes run
-// the interaction loop, FP32 per tile, tiles merged with compensated (Kahan)
-// summation.  No list leaves the chip.
+// offsets from the group centre plus mass; every 64 of them all lanes run the
+// interaction loop, per tile in FP32 (precision 0) or FP64 (precision 1),
+// tiles merged with compensated (Kahan) summation.  No list leaves the chip.
 //
 // The stack stays bounded: every popped node pushes at most one range, so a
 // step may take `want` nodes only while top + want leaves a reserve of 22
@@ -27,10 +27,11 @@
 // Hard force (section II.C, eq. 10): per group, a walk that opens every node
 // whose box (the bounding box of its particles' master positions, kept
 // current by a refit after each drift) lies within R2 (plus rounding slack)
-// of the group box collects candidate leaves; their particles are filtered against the group box, then
-// every candidate pair is decided by the exact FP64 test
-// fma(dz,dz, fma(dy,dy, dx*dx)) < R2^2 on the master positions, and accepted
-// pairs add K(r) times the softened pair force, summed in FP64.
+// of the group box collects candidate leaves; their particles are filtered
+// against the group box, then every candidate pair is decided by the exact
+// FP64 test fma(dz,dz, fma(dy,dy, dx*dx)) < R2^2 on the master positions, and
+// accepted pairs add K(r) times the softened pair force, in FP64.  The hard
+// kernel has its own group table (cells of at most 64 particles).
 #include "htree_dev.h"
 
 #include <math.h>
