@@ -92,11 +92,35 @@ def cpu_baseline(wl, x, m64, seconds_hint=20.0):
     t0 = time.perf_counter()
     _, _, inter = T.soft(1.0, wl.eps, wl.R1, wl.R2, 1, groups=groups)
     dt = time.perf_counter() - t0
+    # the other phases, for context: the hard force (direct neighbour sums) on
+    # a sample of sinks, and the direct force on a sample, both scaled to N
+    n = x.shape[1]
+    hs = synth.sample_indices(n, 4096, 9)
+    t0 = time.perf_counter()
+    oracle.split_direct(x, m64, 1.0, wl.eps, wl.R1, wl.R2, sinks=hs, soft=False)
+    t_hard = (time.perf_counter() - t0) * n / len(hs)
+    ds = synth.sample_indices(n, 1024, 10)
+    t0 = time.perf_counter()
+    oracle.direct(x, m64, 1.0, wl.eps, sinks=ds)
+    t_direct = (time.perf_counter() - t0) * n / len(ds)
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": inter / dt, "unit": "interactions/s", "cores": oracle.threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": cpu,
             "sample": "FP64 oracle soft force (walk + interactions) for %d of %d sink groups "
                       "of the N=2^20 Plummer tree (%d interactions, %.1f s; tree build %.1f s "
-                      "not included)" % (k2, ng, inter, dt, t_build)}
+                      "not included)" % (k2, ng, inter, dt, t_build),
+            "phases_s": {"tree_build": t_build,
+                         "soft_all_groups_extrapolated": dt * ng / k2,
+                         "hard_extrapolated_from_4096_sinks": t_hard,
+                         "direct_extrapolated_from_1024_sinks": t_direct}}
 
 
 def _log(msg):
@@ -415,15 +439,21 @@ def main():
         print("bench: warmup step %d done" % k, file=sys.stderr, flush=True)
     t.stats()                                # reset counters and event timings
     torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
     t0 = time.perf_counter()
     for k in range(args.steps):
+        evs[k][0].record(t.stream)
         t.step(1)
+        evs[k][1].record(t.stream)
     t.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     st = t.stats()
     K = args.steps
     ms_step = 1e3 * wall / K
+    step_ms = sorted(e0.elapsed_time(e1) for e0, e1 in evs)
+    ms_median = step_ms[len(step_ms) // 2]
     soft_inter = st["soft_interactions"] / K
     hard_pairs = st["hard_pairs"] / K
     value = (soft_inter + hard_pairs) / (wall / K)
@@ -443,6 +473,7 @@ def main():
         "warmup": args.warmup,
         "ms_per_step": ms_step,
         "s_per_step": ms_step / 1e3,
+        "s_per_step_median": ms_median / 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
