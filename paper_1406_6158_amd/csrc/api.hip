@@ -341,11 +341,13 @@ void ev_end(htree_ctx *c, int k) {
     c->ev_n[k]++;
 }
 
-htree_status do_build(htree_ctx *c, bool moments) {
+// keep_acc: permute the kept accelerations too (not needed when both forces
+// are computed right after the build).
+htree_status do_build(htree_ctx *c, bool moments, bool keep_acc = true) {
     ev_begin(c, 0);
     launch_bbox_keys(c->B, c->stream);
     launch_sort(c->B, c->stream);
-    launch_gather(c->B, c->stream);
+    launch_gather(c->B, keep_acc, c->stream);
     launch_topology(c->B, moments, c->stream);
     launch_groups(c->B, c->stream);
     ev_end(c, 0);
@@ -411,7 +413,7 @@ htree_status kick(htree_ctx *c, double ks, double kh, double dt_drift) {
 
 htree_status ensure_forces(htree_ctx *c) {
     if (c->forces_current) return HTREE_OK;
-    htree_status st = do_build(c, true);
+    htree_status st = do_build(c, true, false);
     if (st) return st;
     if ((st = do_soft(c))) return st;
     if (c->p.hybrid && (st = do_hard(c))) return st;
@@ -581,7 +583,7 @@ htree_status htree_step(htree_ctx *c, int32_t n_soft) {
     for (int32_t s = 0; s < n_soft; s++) {
         if (!c->p.hybrid) {
             if ((st = kick(c, 0.5 * dts, 0.0, dts))) return st;
-            if ((st = do_build(c, true))) return st;
+            if ((st = do_build(c, true, false))) return st;
             if ((st = do_soft(c))) return st;
             if ((st = kick(c, 0.5 * dts, 0.0, 0.0))) return st;
             c->forces_current = true;
@@ -595,7 +597,7 @@ htree_status htree_step(htree_ctx *c, int32_t n_soft) {
             // a full build where the soft force needs it, a refit of the
             // node boxes on the other substeps
             const bool last = h == nsub - 1;
-            if ((st = last ? do_build(c, true) : do_refit(c))) return st;
+            if ((st = last ? do_build(c, true, false) : do_refit(c))) return st;
             if (last && (st = do_soft(c))) return st;
             if ((st = do_hard(c))) return st;
             if ((st = kick(c, last ? 0.5 * dts : 0.0, 0.5 * dth, 0.0))) return st;

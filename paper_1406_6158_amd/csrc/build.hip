@@ -408,6 +408,7 @@ void launch_sort(BuildBufs &B, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // permutation of the particle state into key order
 // ---------------------------------------------------------------------------
+template <bool ACC>
 __global__ __launch_bounds__(256) void k_gather(
     const uint32_t *idx, int64_t n, const uint32_t *sys_of, const Frame *frames, const double *x0,
     const float *v0, const float *m0, const uint32_t *p0, const float *as0, const float *ah0,
@@ -421,8 +422,10 @@ __global__ __launch_bounds__(256) void k_gather(
         xx[a] = x0[a * n + o];
         x1[a * n + p] = xx[a];
         v1[a * n + p] = v0[a * n + o];
-        as1[a * n + p] = as0[a * n + o];
-        ah1[a * n + p] = ah0[a * n + o];
+        if (ACC) {
+            as1[a * n + p] = as0[a * n + o];
+            ah1[a * n + p] = ah0[a * n + o];
+        }
     }
     float mm = m0[o];
     m1[p] = mm;
@@ -430,12 +433,20 @@ __global__ __launch_bounds__(256) void k_gather(
     src[p] = make_double4(xx[0] - F.lo[0], xx[1] - F.lo[1], xx[2] - F.lo[2], (double)mm);
 }
 
-void launch_gather(BuildBufs &B, hipStream_t s) {
+// Permutes the state into the new key order.  The kept accelerations follow
+// only if keep_acc (callers that recompute both forces next skip them).
+void launch_gather(BuildBufs &B, bool keep_acc, hipStream_t s) {
     int c = B.cur, d = c ^ 1;
     int64_t n = B.n;
-    hipLaunchKernelGGL(k_gather, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, B.idx[0], n,
-                       B.sys_of, B.frame, B.x[c], B.v[c], B.m[c], B.perm[c], B.as[c], B.ah[c],
-                       B.x[d], B.v[d], B.m[d], B.perm[d], B.as[d], B.ah[d], B.src);
+    const dim3 grid((unsigned)((n + 255) / 256));
+    if (keep_acc)
+        hipLaunchKernelGGL(k_gather<true>, grid, dim3(256), 0, s, B.idx[0], n, B.sys_of, B.frame,
+                           B.x[c], B.v[c], B.m[c], B.perm[c], B.as[c], B.ah[c], B.x[d], B.v[d],
+                           B.m[d], B.perm[d], B.as[d], B.ah[d], B.src);
+    else
+        hipLaunchKernelGGL(k_gather<false>, grid, dim3(256), 0, s, B.idx[0], n, B.sys_of,
+                           B.frame, B.x[c], B.v[c], B.m[c], B.perm[c], B.as[c], B.ah[c], B.x[d],
+                           B.v[d], B.m[d], B.perm[d], B.as[d], B.ah[d], B.src);
     B.cur = d;
 }
 
@@ -652,7 +663,8 @@ __global__ __launch_bounds__(256) void k_level_pass(Node *node, const double4 *s
 // from their particle ranges, which needs no level order.  Boxes of aligned
 // chunks of 32, 32^2 and 32^3 sorted particles are reduced first; a node's
 // range is then covered greedily by the largest aligned chunks that fit (at
-// most 31 pieces of each size on either side), one lane per node.  Minima
+// most 31 pieces of each size on either side), one lane per node, nodes in
+// pre-order.  Minima
 // and maxima are exact, so the boxes equal those of the level pass.
 constexpr int kC1 = 32;
 
@@ -686,12 +698,15 @@ __global__ __launch_bounds__(256) void k_box32(const double *x, const double *sr
 }
 
 __global__ __launch_bounds__(256) void k_refit(const Node *node, const uint32_t *nn_dev,
-                                               const double *x, int64_t n, const double *c1,
-                                               int64_t m1, const double *c2, int64_t m2,
-                                               const double *c3, int64_t m3, double *aabb,
-                                               int64_t nnmax) {
-    const uint32_t b = blockIdx.x * 256 + threadIdx.x;
-    if (b >= *nn_dev) return;
+                                               const uint32_t *pre2bfs, const double *x,
+                                               int64_t n, const double *c1, int64_t m1,
+                                               const double *c2, int64_t m2, const double *c3,
+                                               int64_t m3, double *aabb, int64_t nnmax) {
+    // threads take nodes in pre-order, so neighbouring lanes hold leaves with
+    // adjacent particle ranges and their loads share cache lines
+    const uint32_t p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= *nn_dev) return;
+    const uint32_t b = pre2bfs[p];
     const uint32_t f = node[b].first, e = f + node[b].count;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     auto box = [&](const double *t, int64_t m, int64_t k) {
@@ -747,7 +762,7 @@ void launch_refit(BuildBufs &B, hipStream_t s) {
     hipLaunchKernelGGL(k_box32, dim3((unsigned)((m2 + 255) / 256)), dim3(256), 0, s, nullptr, c2,
                        m2, c3, m3);
     hipLaunchKernelGGL(k_refit, dim3((unsigned)((B.nnmax + 255) / 256)), dim3(256), 0, s, B.node,
-                       B.nn, x, n, c1, m1, c2, m2, c3, m3, B.aabb, B.nnmax);
+                       B.nn, B.pre2bfs, x, n, c1, m1, c2, m2, c3, m3, B.aabb, B.nnmax);
 }
 
 // The bottom-up pass over all levels (lstart must be current): node boxes,

@@ -171,7 +171,7 @@ struct BuildBufs {
 // Host launch wrappers (build.hip).
 void launch_bbox_keys(const BuildBufs &B, hipStream_t s);
 void launch_sort(BuildBufs &B, hipStream_t s);
-void launch_gather(BuildBufs &B, hipStream_t s);
+void launch_gather(BuildBufs &B, bool keep_acc, hipStream_t s);
 void launch_topology(BuildBufs &B, bool moments, hipStream_t s);
 void launch_levels(BuildBufs &B, bool moments, hipStream_t s);
 void launch_refit(BuildBufs &B, hipStream_t s);
