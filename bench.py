@@ -35,7 +35,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic FP32 flops per interaction (see DESIGN.md): a monopole or far
+# Algorithmic FP32 flops per interaction: a monopole or far
 # particle term is 3 sub, 3 fma (r^2 + eps^2), 1 rsqrt, 3 mul, 3 fma (FMA = 2
 # flops) = 19; a near particle term adds the unsoftened r^2 (5), sqrt (1) and
 # the (1 - K) polynomial and weight (7) = 32.

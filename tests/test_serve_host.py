@@ -51,3 +51,26 @@ def test_footprint_is_workspace_plus_outputs(abi, hybrid, flags):
 def test_footprint_invalid_is_zero(abi):
     assert abi.solve_footprint(abi.default_params(eps=0.0), 100) == 0
     assert abi.solve_footprint(abi.default_params(), 0) == 0
+
+
+def test_server_argument_errors(abi):
+    """Argument checks that come before any device call."""
+    import ctypes as C
+    L = abi.lib()
+    h = C.c_void_p()
+    streams = (C.c_void_p * 1)(None)
+    # NULL or misaligned arena
+    assert L.htree_server_create(C.byref(h), None, 1 << 20, streams, 1, 1) == abi.HTREE_EINVAL
+    assert L.htree_server_create(C.byref(h), C.c_void_p(0x1001), 1 << 20, streams, 1, 1) == abi.HTREE_EINVAL
+    # stream and depth limits
+    assert L.htree_server_create(C.byref(h), C.c_void_p(0x1000), 1 << 20, streams, 0, 1) == abi.HTREE_EINVAL
+    assert L.htree_server_create(C.byref(h), C.c_void_p(0x1000), 1 << 20, streams, 1, 17) == abi.HTREE_EINVAL
+    assert L.htree_server_create(C.byref(h), C.c_void_p(0x1000), 1 << 20, None, 1, 1) == abi.HTREE_EINVAL
+    # calls on a NULL server
+    rid = C.c_int64()
+    p = abi.default_params()
+    assert L.htree_server_submit(None, C.byref(p), 10, None, 10, None, C.byref(rid)) == abi.HTREE_EINVAL
+    nd = C.c_int32()
+    assert L.htree_server_poll(None, None, 0, C.byref(nd)) == abi.HTREE_EINVAL
+    assert L.htree_server_release(None, 1) == abi.HTREE_EINVAL
+    L.htree_server_destroy(None)
