@@ -147,10 +147,12 @@ htree_status htree_kick_drift(htree_ctx *ctx, double dt_kick, const float *d_acc
 
 /* Advances n_soft_steps soft steps with the nested kick-drift-kick of
  * section II.C (one soft-step plus n_sub - 1 hard-steps per dt_s): per soft
- * step v += dt_s/2 a_s; n_sub times { v += dt_h/2 a_h; x += dt_h v; rebuild;
- * last substep: a_s = soft, a_h = hard, else a_h = hard; v += dt_h/2 a_h };
- * v += dt_s/2 a_s.  Plain mode: n_sub = 1 with the full tree force.  Forces at
- * the initial positions are computed on the first call. */
+ * step v += dt_s/2 a_s; n_sub times { v += dt_h/2 a_h; x += dt_h v;
+ * last substep: rebuild, a_s = soft, a_h = hard; other substeps: refit the
+ * node boxes to the drifted positions (same tree and groups), a_h = hard;
+ * v += dt_h/2 a_h }; v += dt_s/2 a_s.  The hard force's neighbour sets are
+ * exact either way.  Plain mode: n_sub = 1 with the full tree force.  Forces
+ * at the initial positions are computed on the first call. */
 htree_status htree_step(htree_ctx *ctx, int32_t n_soft_steps);
 
 /* Copies positions / velocities out in caller order (either may be NULL). */
