@@ -7,10 +7,12 @@ hard forces and the kicks and drifts, all inside libhtree on the GPU.
 
 Prints one JSON line.  ``value`` is the whole-job interaction rate: (soft
 interactions + accepted hard pairs) per step divided by the step time.  The
-``roofline`` object describes the dominant kernel (the soft walk+interaction
-kernel), timed with HIP events recorded by the library on its stream over the
-timed steps; ``cpu_baseline`` times the FP64 oracle on the host cores on a
-bounded sample of the same workload.
+``roofline`` object describes the dominant kernel by time (the hard kernel:
+FP64 pair tests and pair forces), ``roofline_interaction`` the soft walk +
+FP32 interaction kernel; both are timed with HIP events recorded by the
+library on its stream around each launch over the timed steps.
+``cpu_baseline`` times the FP64 oracle on the host cores on a bounded sample
+of the same workload.
 
 Two further sections run after the timed steps and are reported beside
 them: ``ensemble`` (512 independent Plummer clusters, N log-uniform in
@@ -41,6 +43,13 @@ if ROOT not in sys.path:
 # the (1 - K) polynomial and weight (7) = 32.
 FLOPS_FAR = 19
 FLOPS_NEAR = 32
+# Algorithmic FP64 flops of the hard kernel: a candidate pair test is 3 sub,
+# 1 mul, 2 fma (r^2) = 8; an accepted pair adds r^2 + eps^2 (1), two
+# 1/sqrt (seed 1 + Newton step 5 each, the second times r^2: +1), K(r) (10),
+# the force factor (4) and 3 fma (6), with its offsets and r^2 again (8) = 42.
+FLOPS_HARD_TEST = 8
+FLOPS_HARD_PAIR = 42
+PEAK_FP64 = 78.6
 # MI355X vector peaks derived from the unit counts: 256 CUs x 4 SIMD x 16 lanes
 # x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s for non-packed FP32 (the build
 # disables packed FP32); the published packed figure is 157.3 TFLOP/s.
@@ -53,6 +62,7 @@ PEAK_FP32_PACKED = 157.3
 # for the kernel source it was measured on: reported as null once force.hip or
 # htree_dev.h differ from that source.
 SOFT_TRAFFIC = {"bytes": 1439.8e6, "source_hash": "0f43bf3969cb557f"}
+HARD_TRAFFIC = {"bytes": 1546.0e6, "source_hash": "0f43bf3969cb557f"}
 
 
 def _kernel_source_hash():
@@ -458,12 +468,18 @@ def main():
     hard_pairs = st["hard_pairs"] / K
     value = (soft_inter + hard_pairs) / (wall / K)
 
-    # dominant kernel: the soft walk + interaction kernel
+    # the soft walk + interaction kernel
     calls = max(st["calls_soft"], 1)
     soft_ms = st["ms_soft"] / calls
     near_frac = st["soft_near"] / max(st["soft_cells"] + st["soft_far"] + st["soft_near"], 1)
     flops = soft_inter * (FLOPS_FAR * (1 - near_frac) + FLOPS_NEAR * near_frac)
     achieved = flops / (soft_ms * 1e-3) / 1e12
+    # the dominant kernel by time: the hard kernel (one launch per substep)
+    hcalls = max(st["calls_hard"], 1)
+    hard_ms = st["ms_hard"] / hcalls
+    hflops = (FLOPS_HARD_TEST * st["hard_candidates"] + FLOPS_HARD_PAIR * st["hard_pairs"]) / hcalls
+    hachieved = hflops / (hard_ms * 1e-3) / 1e12
+    src_ok = _kernel_source_hash() == SOFT_TRAFFIC["source_hash"]
     line = {
         "metric": "interactions/s + s/step at N=2^20 Plummer; batched p50/p99 solve latency",
         "value": value,
@@ -488,13 +504,19 @@ def main():
         "soft_kernel_interactions_per_s": soft_inter / (soft_ms * 1e-3),
         "phase_ms_per_step": {"build": st["ms_build"] / K, "soft": st["ms_soft"] / K,
                               "hard": st["ms_hard"] / K},
-        "roofline": {"kernel": "k_soft (walk + FP32 interactions)", "bound": "alu",
-                     "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32,
-                     "frac_of_packed_fp32_peak": achieved / PEAK_FP32_PACKED,
-                     "traffic": (SOFT_TRAFFIC["bytes"]
-                                 if _kernel_source_hash() == SOFT_TRAFFIC["source_hash"] else None),
-                     "traffic_unit": "bytes per launch (HBM, counter-measured)"},
+        "roofline": {"kernel": "k_hard (R2 walk + exact FP64 pair tests + FP64 pair forces)",
+                     "bound": "alu", "achieved": hachieved, "peak": PEAK_FP64,
+                     "unit": "TFLOP/s", "frac": hachieved / PEAK_FP64,
+                     "traffic": HARD_TRAFFIC["bytes"] if src_ok else None,
+                     "traffic_unit": "bytes per launch (HBM, counter-measured)",
+                     "launch_ms": hard_ms, "share_of_step": st["ms_hard"] / K / ms_step},
+        "roofline_interaction": {"kernel": "k_soft (walk + FP32 interactions)", "bound": "alu",
+                                 "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
+                                 "frac": achieved / PEAK_FP32,
+                                 "frac_of_packed_fp32_peak": achieved / PEAK_FP32_PACKED,
+                                 "traffic": SOFT_TRAFFIC["bytes"] if src_ok else None,
+                                 "traffic_unit": "bytes per launch (HBM, counter-measured)",
+                                 "launch_ms": soft_ms, "share_of_step": st["ms_soft"] / K / ms_step},
         "cpu_baseline": None,
     }
     t.close()
