@@ -22,7 +22,7 @@ contexts) and ``serving`` (Poisson arrivals at 500/s of force solves with N
 log-uniform in [2^12, 2^20], admitted by HBM footprint into the request
 server, p50/p99 latency).
 
-    python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--no-cpu-baseline]
+    python bench.py [--gpus 1] [--steps 16] [--warmup 1] [--no-cpu-baseline]
                     [--no-ensemble] [--no-serve] [--serve-requests 20000]
 """
 from __future__ import annotations
@@ -397,7 +397,7 @@ def serving(P, torch, n_req, warm, arena_bytes, label, pool_per_model=2):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=16)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ensemble", action="store_true")
