@@ -229,16 +229,18 @@ __device__ inline void eval_near(const vec4_t<T> *t, int cnt, T sx, T sy, T sz, 
     if (POT) kahan(A.p, A.pc, ph);
 }
 
-// Takes `want` items from the top of a range stack (first[], cnt[], nr
-// ranges, each count >= 1, the top 64 ranges holding at least `want` items),
-// consuming each range from its end.  Returns this lane's item (lane < want).
-// All lanes must call it.
+// Takes `want` items from the top of a range stack (nr ranges, each count
+// >= 1, the top 64 ranges holding at least `want` items), consuming each range
+// from its end.  Range q (0 = bottom) is held in first[O.slot(q)],
+// cnt[O.slot(q)].  Returns this lane's item (lane < want).  All lanes must
+// call it.
+template <typename Order>
 __device__ inline uint32_t take_items(uint32_t *first, uint32_t *cnt, int &nr, int want,
-                                      uint32_t *scan) {
+                                      uint32_t *scan, const Order &O) {
     const int lane = __lane_id();
     HT_CHECK(want >= 1 && want <= 64 && nr >= 1);
     int r = nr < 64 ? nr : 64;
-    uint32_t ck = lane < r ? cnt[nr - 1 - lane] : 0u;
+    uint32_t ck = lane < r ? cnt[O.slot(nr - 1 - lane)] : 0u;
     uint32_t inc = wave_incl_scan(ck);
     scan[lane] = inc;
     __syncthreads();
@@ -250,7 +252,8 @@ __device__ inline uint32_t take_items(uint32_t *first, uint32_t *cnt, int &nr, i
             if (scan[mid] > (uint32_t)lane) hi = mid; else lo = mid + 1;
         }
         uint32_t prev = lo ? scan[lo - 1] : 0u;
-        uint32_t f = first[nr - 1 - lo], c = cnt[nr - 1 - lo];
+        const int sl = O.slot(nr - 1 - lo);
+        uint32_t f = first[sl], c = cnt[sl];
         item = f + c - 1u - ((uint32_t)lane - prev);
     }
     HT_CHECK(__shfl(inc, r - 1) >= (uint32_t)want);
@@ -258,10 +261,20 @@ __device__ inline uint32_t take_items(uint32_t *first, uint32_t *cnt, int &nr, i
     int nfull = __popcll(full);
     uint32_t used = nfull ? __shfl(inc, nfull - 1) : 0u;
     __syncthreads();
-    if (lane == 0 && (uint32_t)want > used) cnt[nr - 1 - nfull] -= (uint32_t)want - used;
+    if (lane == 0 && (uint32_t)want > used) cnt[O.slot(nr - 1 - nfull)] -= (uint32_t)want - used;
     nr -= nfull;
     __syncthreads();
     return item;
+}
+
+// Ranges stored in stack order: position q is entry q.
+struct StackOrder {
+    __device__ int slot(int q) const { return q; }
+};
+
+__device__ inline uint32_t take_items(uint32_t *first, uint32_t *cnt, int &nr, int want,
+                                      uint32_t *scan) {
+    return take_items(first, cnt, nr, want, scan, StackOrder{});
 }
 
 // Number of nodes a walk step may take: up to 64, keeping room for one pushed
@@ -515,14 +528,57 @@ void launch_soft(const ForceArgs &A, bool hybrid, bool pot, int precision, int n
 // ---------------------------------------------------------------------------
 // hard force
 // ---------------------------------------------------------------------------
-constexpr int kStkHard = 256;      // the R2 walk opens few nodes
+constexpr int kHardEnt = 472;      // walk stack and leaf batch share these entries
 constexpr int kStage = 192;        // staged candidates: up to 127 waiting + one gather of 64
 
+// 10176 bytes: 16 wavefronts of this kernel fit the 160 KiB of a CU.
 struct HardLDS {
-    uint32_t sfirst[kStkHard], scnt[kStkHard];
+    // walk stack (child ranges) in entries [0, top), the batch of collected
+    // leaves (particle ranges) in entries [kHardEnt - nl, kHardEnt)
+    uint32_t efirst[kHardEnt], ecnt[kHardEnt];
     double4 tq[kStage];            // staged candidate: master x, y, z and mass
-    uint32_t rfirst[kRQ], rcnt[kRQ];
     uint32_t scan[64];
+};
+
+// Gather order of a batch of nl collected leaves (leaf k in entry
+// kHardEnt - 1 - k).  Consumption position q reads leaf (q * p) mod nl, with
+// p the integer nearest nl (1 - 1/phi) that is coprime to nl (a bijection).
+// Consecutive gathers so draw leaves from all over the batch, which spreads
+// the pairs accepted in one stage over the group's sinks instead of piling
+// them onto the few sinks next to one leaf; the accepted-pair loop runs as
+// many times as the busiest lane needs.
+struct LeafOrder {
+    uint32_t nl = 1, p = 1;
+    float inv = 1.0f;
+
+    __device__ static LeafOrder make(uint32_t nl) {
+        LeafOrder O;
+        O.nl = nl;
+        uint32_t p = (uint32_t)(0.381966f * (float)nl + 0.5f);
+        if (p < 1u) p = 1u;
+        for (;; p++) {            // gcd(p, nl) == 1; p = nl - 1 always is
+            uint32_t a = nl, b = p;
+            while (b) {
+                uint32_t t = a % b;
+                a = b;
+                b = t;
+            }
+            if (a == 1u) break;
+        }
+        O.p = p;
+        O.inv = 1.0f / (float)nl;
+        return O;
+    }
+    // (q * p) mod nl for q < nl <= kHardEnt: q * p < 2^18 is exact in FP32 and
+    // the quotient estimate is off by at most one either way.
+    __device__ int slot(int q) const {
+        const uint32_t t = (uint32_t)q * p;
+        const uint32_t k = (uint32_t)((float)t * inv);
+        int r = (int)(t - k * nl);
+        if (r < 0) r += (int)nl;
+        if (r >= (int)nl) r -= (int)nl;
+        return kHardEnt - 1 - r;
+    }
 };
 
 // Pair tests of this lane's sink against 64 staged candidates (or `cnt` < 64
@@ -590,11 +646,11 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
     // removed from the neighbour count at the end.
     double hx = 0.0, hy = 0.0, hz = 0.0;
     uint32_t ngb = 0, cand = 0;
-    int top = 1, nr = 0, nst = 0;
+    int top = 1, nl = 0, nr = 0, nst = 0;
     uint32_t avail = 1, tot = 0;
     if (lane == 0) {
-        S.sfirst[0] = sys;
-        S.scnt[0] = 1;
+        S.efirst[0] = sys;
+        S.ecnt[0] = 1;
     }
     __syncthreads();
 
@@ -635,16 +691,17 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
         nst -= cnt;
     };
 
-    // Gathers of candidate particles from the leaf ranges, in two halves so
-    // that the loads of one gather are in flight while staged pairs are
+    // Gathers of candidate particles from the batch of leaves, in two halves
+    // so that the loads of one gather are in flight while staged pairs are
     // evaluated: issue() takes up to 64 particles and starts their loads,
     // finish() keeps those within R2 (plus slack) of the sink box.
+    LeafOrder order;
     uint32_t g_pi = 0;
     int g_want = 0;
     double gx = 0.0, gy = 0.0, gz = 0.0;
     float gm = 0.0f;
     auto issue = [&](int want) {
-        g_pi = take_items(S.rfirst, S.rcnt, nr, want, S.scan);
+        g_pi = take_items(S.efirst, S.ecnt, nr, want, S.scan, order);
         g_want = want;
         if (lane < want) {
             gx = A.x[g_pi];
@@ -667,23 +724,35 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
         g_want = 0;
         __syncthreads();
     };
-    // drains full gathers, overlapping each gather's loads with evaluation
-    auto drain = [&]() {
+    // gathers every particle of the collected leaves in the batch's order,
+    // overlapping each gather's loads with evaluation; empties the batch
+    auto drain_batch = [&]() {
+        order = LeafOrder::make((uint32_t)nl);
+        nr = nl;
         bool pending = false;
         for (;;) {
             if (pending) finish();
-            pending = tot >= 64;
-            if (pending) issue(64);
+            pending = tot > 0;
+            if (pending) issue(tot < 64u ? (int)tot : 64);
             if (nst >= 128) eval_top(128);
             if (!pending) break;
         }
+        HT_CHECK(nr == 0);
+        nl = 0;
     };
 
+    // The walk collects leaves into the batch until the shared entries run
+    // short, then the batch is gathered.
     while (avail > 0) {
+        // one entry beyond the depth-first reserve is kept for a leaf
+        int room = kHardEnt - kStkReserve - 1 - top - nl;
+        if (nl > 0 && room < 64) {
+            drain_batch();
+            room = kHardEnt - kStkReserve - 1 - top;
+        }
         int want = avail < 64u ? (int)avail : 64;
-        const int room = kStkHard - kStkReserve - top;
         if (want > room) want = room > 1 ? room : 1;
-        uint32_t id = take_items(S.sfirst, S.scnt, top, want, S.scan);
+        uint32_t id = take_items(S.efirst, S.ecnt, top, want, S.scan);
         avail -= (uint32_t)want;
         const bool have = lane < want;
         bool leaf = false, opn = false;
@@ -705,28 +774,24 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
         }
         uint64_t m = __ballot(leaf);
         if (leaf) {
-            int o = nr + __popcll(m & lt);
-            S.rfirst[o] = first;
-            S.rcnt[o] = count;
+            int o = kHardEnt - 1 - (nl + __popcll(m & lt));
+            S.efirst[o] = first;
+            S.ecnt[o] = count;
         }
-        nr += __popcll(m);
+        nl += __popcll(m);
         tot += wave_sum(leaf ? count : 0u);
         m = __ballot(opn);
         if (opn) {
             int o = top + __popcll(m & lt);
-            S.sfirst[o] = child;
-            S.scnt[o] = nch;
+            S.efirst[o] = child;
+            S.ecnt[o] = nch;
         }
         top += __popcll(m);
         avail += wave_sum(opn ? nch : 0u);
-        HT_CHECK(top <= kStkHard && nr < kRQ && nst < kStage);
+        HT_CHECK(top + nl <= kHardEnt && nst < kStage);
         __syncthreads();
-        drain();
     }
-    if (tot > 0) {
-        issue((int)tot);
-        finish();
-    }
+    if (nl > 0) drain_batch();
     while (nst > 0) eval_top(nst < 128 ? nst : 128);
 
     if (act) {
@@ -744,7 +809,7 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
     }
 }
 
-__global__ __launch_bounds__(64) void k_hard(ForceArgs A) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_hard(ForceArgs A) {
     __shared__ HardLDS S;
     const uint32_t ng = *A.ng;
     for (uint32_t idx = blockIdx.x; idx < ng; idx += gridDim.x) {
