@@ -667,20 +667,20 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
         }
         if (!act) m0 = m1 = 0;
         ngb += __popcll(m0) + __popcll(m1);
+        int off = 0;
         while (m0 | m1) {
-            int s;
-            if (m0) {
-                s = __ffsll((long long)m0) - 1;
-                m0 &= m0 - 1;
-            } else {
-                s = 63 + __ffsll((long long)m1);
-                m1 &= m1 - 1;
-            }
+            // bits of the high word move down once the low word is spent
+            const bool sw = m0 == 0;
+            m0 = sw ? m1 : m0;
+            m1 = sw ? 0 : m1;
+            off = sw ? 64 : off;
+            const int s = off + (int)__builtin_ctzll(m0);
+            m0 &= m0 - 1;
             const double4 q = S.tq[base + s];
             double dx = q.x - xi, dy = q.y - yi, dz = q.z - zi;
             double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
             double ri = rsqrt64(r2 + eps2d);
-            double r = r2 > 1e-30 ? r2 * rsqrt64(r2) : 0.0;   // K = 1 below R1 anyway
+            double r = r2 * rsqrt64(fmax(r2, 1e-30));   // the sink itself: r = 0
             double K = K_of64(r, R2, invdR64);
             double f = q.w * K * (ri * ri * ri);
             hx = fma(f, dx, hx);
