@@ -27,11 +27,13 @@
 // Hard force (section II.C, eq. 10): per group, a walk that opens every node
 // whose box (the bounding box of its particles' master positions, kept
 // current by a refit after each drift) lies within R2 (plus rounding slack)
-// of the group box collects candidate leaves; their particles are filtered
-// against the group box, then every candidate pair is decided by the exact
-// FP64 test fma(dz,dz, fma(dy,dy, dx*dx)) < R2^2 on the master positions, and
-// accepted pairs add K(r) times the softened pair force, in FP64.  The hard
-// kernel has its own group table (cells of at most 64 particles).
+// of the group box collects candidate leaves into a batch; the batch's
+// particles are gathered in a stride order that mixes the leaves (LeafOrder)
+// and filtered against the group box, then every candidate pair is decided
+// by the exact FP64 test fma(dz,dz, fma(dy,dy, dx*dx)) < R2^2 on the master
+// positions, and accepted pairs add K(r) times the softened pair force, in
+// FP64.  The hard kernel has its own group table (cells of at most 64
+// particles).
 #include "htree_dev.h"
 
 #include <math.h>
