@@ -124,7 +124,8 @@ struct htree_ctx {
     float *pot = nullptr;              // [n] key order
     int32_t *ngb = nullptr;            // [n] key order
     uint32_t *gcount = nullptr;        // [3][n] list sizes per group (first ng used)
-    unsigned long long *tally = nullptr;  // [4]
+    unsigned long long *tally = nullptr;      // [kTallySlots][kTallyStride] slots
+    unsigned long long *tally_sum = nullptr;  // [4] their totals (launch_tally_fold)
     int n_wg = 0;                      // force kernel grid
     std::vector<Sys> h_sys;            // host copies of the static tables, kept
     std::vector<SysF> h_sysf;          // alive until the asynchronous upload is
@@ -228,7 +229,8 @@ void carve(Carver &C, htree_ctx *c) {
     c->pot = C.take<float>(n);
     c->ngb = C.take<int32_t>(n);
     c->gcount = C.take<uint32_t>(3 * n);
-    c->tally = C.take<unsigned long long>(4);
+    c->tally = C.take<unsigned long long>(kTallySlots * kTallyStride);
+    c->tally_sum = C.take<unsigned long long>(4);
 }
 
 void setup_sizes(htree_ctx *c, const htree_params *p, const int64_t *n, int32_t S) {
@@ -497,7 +499,7 @@ htree_status htree_batch_create(htree_ctx **out, const htree_params *p, const in
     c->timing = (p[0].flags & HTREE_F_TIMING) != 0;
     launch_zero_u32(c->B.status, 4, c->stream);
     launch_zero_u32(c->B.nn, 4, c->stream);
-    launch_zero_u32((uint32_t *)c->tally, 8, c->stream);
+    launch_zero_u32((uint32_t *)c->tally, 2 * kTallySlots * kTallyStride, c->stream);
     if ((st = upload_tables(c))) {
         delete c;
         return st;
@@ -630,7 +632,9 @@ htree_status htree_stats(htree_ctx *c, htree_counters *out) {
     HIP_OK(hipStreamSynchronize(c->stream));
     unsigned long long t[4];
     uint32_t nn = 0, ng = 0;
-    HIP_OK(hipMemcpy(t, c->tally, sizeof t, hipMemcpyDeviceToHost));
+    launch_tally_fold(c->tally, c->tally_sum, c->stream);
+    HIP_OK(hipMemcpyAsync(t, c->tally_sum, sizeof t, hipMemcpyDeviceToHost, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
     HIP_OK(hipMemcpy(&nn, c->B.nn, sizeof nn, hipMemcpyDeviceToHost));
     HIP_OK(hipMemcpy(&ng, c->B.ng, sizeof ng, hipMemcpyDeviceToHost));
     c->ng = ng;
@@ -668,7 +672,7 @@ htree_status htree_stats(htree_ctx *c, htree_counters *out) {
     out->calls_soft = c->calls[1];
     out->calls_hard = c->calls[2];
     c->calls[0] = c->calls[1] = c->calls[2] = 0;
-    launch_zero_u32((uint32_t *)c->tally, 8, c->stream);
+    launch_zero_u32((uint32_t *)c->tally, 2 * kTallySlots * kTallyStride, c->stream);
     HIP_OK(hipGetLastError());
     return HTREE_OK;
 }
@@ -785,7 +789,8 @@ htree_status htree::ctx_report_async(htree_ctx *c, CtxReport *dst) {
     // the status word and the interaction tallies, copied in stream order
     HIP_OK(hipMemcpyAsync(&dst->status, c->B.status, sizeof(uint32_t), hipMemcpyDeviceToHost,
                           c->stream));
-    HIP_OK(hipMemcpyAsync(dst->tally, c->tally, sizeof dst->tally, hipMemcpyDeviceToHost,
+    launch_tally_fold(c->tally, c->tally_sum, c->stream);
+    HIP_OK(hipMemcpyAsync(dst->tally, c->tally_sum, sizeof dst->tally, hipMemcpyDeviceToHost,
                           c->stream));
     return HTREE_OK;
 }

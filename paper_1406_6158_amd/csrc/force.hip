@@ -135,6 +135,21 @@ __device__ inline double uniform_f64(double v) {
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// First counter of this workgroup's tally slot.
+__device__ inline int tally_slot() { return (int)(blockIdx.x % kTallySlots) * kTallyStride; }
+
+__global__ void k_tally_fold(const unsigned long long *slots, unsigned long long *sum) {
+    const int k = threadIdx.x;
+    if (k >= 4) return;
+    unsigned long long t = 0;
+    for (int j = 0; j < kTallySlots; j++) t += slots[j * kTallyStride + k];
+    sum[k] = t;
+}
+
+void launch_tally_fold(const unsigned long long *slots, unsigned long long *sum, hipStream_t s) {
+    hipLaunchKernelGGL(k_tally_fold, dim3(1), dim3(64), 0, s, slots, sum);
+}
+
 // Group setup shared by both walks.
 struct GroupCtx {
     uint32_t b0;
@@ -491,7 +506,7 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS<T> &S, uint32_t grp) {
             A.gcount[2 * A.n + grp] = n_near;
         }
         unsigned long long ent = (unsigned long long)n_pc + n_far + n_near;
-        atomicAdd(&A.tally[0], (unsigned long long)G.ns * ent);
+        atomicAdd(&A.tally[tally_slot()], (unsigned long long)G.ns * ent);
     }
 }
 
@@ -806,8 +821,8 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
     }
     uint32_t ngb_sum = wave_sum(act ? ngb : 0u);
     if (lane == 0) {
-        atomicAdd(&A.tally[1], (unsigned long long)ns * cand);
-        atomicAdd(&A.tally[2], (unsigned long long)ngb_sum);
+        atomicAdd(&A.tally[tally_slot() + 1], (unsigned long long)ns * cand);
+        atomicAdd(&A.tally[tally_slot() + 2], (unsigned long long)ngb_sum);
     }
 }
 

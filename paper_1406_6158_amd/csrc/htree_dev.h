@@ -181,6 +181,15 @@ void launch_sys_of(BuildBufs &B, hipStream_t s);
 size_t scan_partials(int64_t n);
 void launch_scan_u32(uint32_t *data, int64_t n, uint32_t *part, uint32_t *total, hipStream_t s);
 
+// Interaction tallies (soft interactions, hard candidates, hard pairs) are
+// added by every sink group.  Device-scope atomics of many workgroups on one
+// address serialize, so the counters live in kTallySlots slots, one 128-byte
+// line each, picked by workgroup index; launch_tally_fold sums the slots into
+// four totals.
+constexpr int kTallySlots = 32;
+constexpr int kTallyStride = 16;
+void launch_tally_fold(const unsigned long long *slots, unsigned long long *sum, hipStream_t s);
+
 // Force kernels (force.hip).
 struct ForceArgs {
     const Node *node;
@@ -199,7 +208,7 @@ struct ForceArgs {
     float *pot;               // [n] or null
     int32_t *ngb;             // [n] or null
     uint32_t *gcount;         // [3][n] list sizes per group (first ng used) or null
-    unsigned long long *tally;  // [4] interaction tallies
+    unsigned long long *tally;  // [kTallySlots][kTallyStride] interaction tally slots
     uint32_t *status;
 };
 void launch_soft(const ForceArgs &A, bool hybrid, bool pot, int precision, int n_wg,
