@@ -132,6 +132,7 @@ struct htree_ctx {
     std::vector<uint2> h_chunk;        // surely done (the context's lifetime)
     bool tree = false, moments = false, have_soft = false, have_hard = false;
     bool boxes = false;                // node boxes fit the current positions (hard walk)
+    bool hard_order = false;           // B.horder holds an order for the current hard groups
     bool forces_current = false;
     bool timing = false;
     std::vector<hipEvent_t> ev[3];     // per phase: start/end pairs since the last stats
@@ -225,6 +226,10 @@ void carve(Carver &C, htree_ctx *c) {
     B.ng = C.take<uint32_t>(4);
     B.hgstart = C.take<uint32_t>(n + 1);
     B.nhg = C.take<uint32_t>(4);
+    B.hcost = C.take<uint32_t>(n);
+    B.hkey = C.take<uint32_t>(n);
+    B.hval = C.take<uint32_t>(n);
+    B.horder = C.take<uint32_t>(n);
     c->tmp3 = C.take<float>(3 * n);
     c->pot = C.take<float>(n);
     c->ngb = C.take<int32_t>(n);
@@ -313,6 +318,8 @@ ForceArgs force_args(htree_ctx *c) {
     A.aabb = B.aabb;
     A.nnmax = B.nnmax;
     A.frame = B.frame;
+    A.order = nullptr;
+    A.cost = nullptr;
     A.n = c->n;
     A.acc = nullptr;
     A.pot = nullptr;
@@ -356,6 +363,7 @@ htree_status do_build(htree_ctx *c, bool moments, bool keep_acc = true) {
     HIP_OK(hipGetLastError());
     c->tree = true;
     c->boxes = true;
+    c->hard_order = false;
     c->moments = moments;
     return HTREE_OK;
 }
@@ -395,9 +403,15 @@ htree_status do_hard(htree_ctx *c) {
     A.ng = c->B.nhg;
     A.acc = c->B.ah[c->B.cur];
     A.ngb = c->ngb;
+    // the first launch over new groups measures their costs; later launches
+    // (after refits) dispatch the groups heaviest first
+    A.order = c->hard_order ? c->B.horder : nullptr;
+    A.cost = c->hard_order ? nullptr : c->B.hcost;
     ev_begin(c, 2);
     launch_hard(A, c->n_wg, c->stream);
+    if (!c->hard_order) launch_hard_order(c->B, c->stream);
     ev_end(c, 2);
+    c->hard_order = true;
     HIP_OK(hipGetLastError());
     c->have_hard = true;
     return HTREE_OK;
@@ -782,6 +796,7 @@ htree_status htree::ctx_set_state(htree_ctx *c, const double *d_x, int64_t ldx, 
     launch_zero_u32((uint32_t *)B.ah[0], 3 * c->n, c->stream);
     HIP_OK(hipGetLastError());
     c->tree = c->moments = c->boxes = c->have_soft = c->have_hard = c->forces_current = false;
+    c->hard_order = false;
     return HTREE_OK;
 }
 

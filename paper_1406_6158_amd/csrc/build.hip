@@ -405,6 +405,33 @@ void launch_sort(BuildBufs &B, hipStream_t s) {
     }
 }
 
+// Dispatch order of the hard groups for the next launches over the same
+// groups: heaviest first (by the costs the last launch measured), so that the
+// expensive groups of dense regions do not start late and leave a tail of a
+// few long workgroups.  Costs are bucketed at a quarter octave; the stable
+// sort keeps key order inside a bucket.
+__global__ __launch_bounds__(256) void k_hard_order_keys(const uint32_t *cost, const uint32_t *nhg,
+                                                         uint32_t *key, uint32_t *val) {
+    const uint32_t g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= *nhg) return;
+    const uint32_t c = cost[g];
+    uint32_t b = 0;
+    if (c > 0) {
+        const uint32_t e = 31u - (uint32_t)__builtin_clz(c);
+        const uint32_t f = e >= 2 ? (c >> (e - 2)) & 3u : (c << (2 - e)) & 3u;
+        b = 4 * e + f;                      // <= 127
+    }
+    key[g] = 255u - b;
+    val[g] = g;
+}
+
+void launch_hard_order(BuildBufs &B, hipStream_t s) {
+    const int64_t n = B.n;
+    hipLaunchKernelGGL(k_hard_order_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       B.hcost, B.nhg, B.hkey, B.hval);
+    radix_pass<uint32_t>(B.hkey, B.hval, B.hcost, B.horder, B.hist, B.scan_part, B.nhg, n, 0, s);
+}
+
 // ---------------------------------------------------------------------------
 // permutation of the particle state into key order
 // ---------------------------------------------------------------------------

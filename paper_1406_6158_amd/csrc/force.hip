@@ -662,7 +662,7 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
     // itself passes the test (r = 0) and adds exactly zero force; it is
     // removed from the neighbour count at the end.
     double hx = 0.0, hy = 0.0, hz = 0.0;
-    uint32_t ngb = 0, cand = 0;
+    uint32_t ngb = 0, cand = 0, trips = 0;
     int top = 1, nl = 0, nr = 0, nst = 0;
     uint32_t avail = 1, tot = 0;
     if (lane == 0) {
@@ -683,7 +683,9 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
             m0 = pair_tests<0>(S.tq + base, cnt, xi, yi, zi, R2sq);
         }
         if (!act) m0 = m1 = 0;
-        ngb += __popcll(m0) + __popcll(m1);
+        const uint32_t hits = (uint32_t)(__popcll(m0) + __popcll(m1));
+        ngb += hits;
+        if (A.cost) trips += wave_max_u32(hits);   // trips of the pair loop below
         int off = 0;
         while (m0 | m1) {
             // bits of the high word move down once the low word is spent
@@ -820,6 +822,9 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
         if (A.ngb) A.ngb[i] = (int32_t)ngb;
     }
     uint32_t ngb_sum = wave_sum(act ? ngb : 0u);
+    // work measure for the dispatch order: a pair-loop trip costs about seven
+    // candidate tests
+    if (A.cost && lane == 0) A.cost[grp] = cand + 7u * trips;
     if (lane == 0) {
         atomicAdd(&A.tally[tally_slot() + 1], (unsigned long long)ns * cand);
         atomicAdd(&A.tally[tally_slot() + 2], (unsigned long long)ngb_sum);
@@ -830,7 +835,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __shared__ HardLDS S;
     const uint32_t ng = *A.ng;
     for (uint32_t idx = blockIdx.x; idx < ng; idx += gridDim.x) {
-        const uint32_t grp = sched_group(idx, ng);
+        const uint32_t pos = sched_group(idx, ng);
+        const uint32_t grp = A.order ? A.order[pos] : pos;
         HT_CHECK(grp < ng);
         hard_group(A, S, grp);
     }

@@ -89,6 +89,13 @@ __device__ inline T wave_max(T v) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
     return v;
 }
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t t = (uint32_t)__shfl_xor(v, o);
+        v = t > v ? t : v;
+    }
+    return v;
+}
 __device__ inline uint32_t wave_incl_scan(uint32_t v) {
     const int lane = __lane_id();
     for (int o = 1; o < 64; o <<= 1) {
@@ -166,6 +173,11 @@ struct BuildBufs {
     uint32_t *ng;          // device soft group count
     uint32_t *hgstart;     // [n+1] hard group start positions (nhg + 1 used)
     uint32_t *nhg;         // device hard group count
+    // hard-group dispatch order (measured costs, heaviest first)
+    uint32_t *hcost;       // [n] cost of each hard group in the last launch; sort scratch
+    uint32_t *hkey;        // [n] sort key (descending cost bucket)
+    uint32_t *hval;        // [n] group index before the sort
+    uint32_t *horder;      // [n] dispatch position -> hard group
 };
 
 // Host launch wrappers (build.hip).
@@ -177,6 +189,7 @@ void launch_levels(BuildBufs &B, bool moments, hipStream_t s);
 void launch_refit(BuildBufs &B, hipStream_t s);
 void refit_sizes(int64_t n, int64_t *m1, int64_t *m2, int64_t *m3);
 void launch_groups(BuildBufs &B, hipStream_t s);
+void launch_hard_order(BuildBufs &B, hipStream_t s);
 void launch_sys_of(BuildBufs &B, hipStream_t s);
 size_t scan_partials(int64_t n);
 void launch_scan_u32(uint32_t *data, int64_t n, uint32_t *part, uint32_t *total, hipStream_t s);
@@ -203,6 +216,8 @@ struct ForceArgs {
     const double *aabb;       // [6][nnmax] node boxes, master coordinates
     int64_t nnmax;
     const Frame *frame;       // [S]
+    const uint32_t *order;    // null, or dispatch position -> group (a permutation)
+    uint32_t *cost;           // null, or [ng] per-group work measure written by the hard kernel
     int64_t n;
     float *acc;               // [3][n] sorted order output
     float *pot;               // [n] or null
