@@ -234,6 +234,9 @@ void carve(Carver &C, htree_ctx *c) {
     c->pot = C.take<float>(n);
     c->ngb = C.take<int32_t>(n);
     c->gcount = C.take<uint32_t>(3 * n);
+    B.wsoft[0] = C.take<uint32_t>(n);
+    B.wsoft[1] = C.take<uint32_t>(n);
+    B.sorder = C.take<uint32_t>(n);
     c->tally = C.take<unsigned long long>(kTallySlots * kTallyStride);
     c->tally_sum = C.take<unsigned long long>(4);
 }
@@ -320,6 +323,7 @@ ForceArgs force_args(htree_ctx *c) {
     A.frame = B.frame;
     A.order = nullptr;
     A.cost = nullptr;
+    A.wsoft = nullptr;
     A.n = c->n;
     A.acc = nullptr;
     A.pot = nullptr;
@@ -359,6 +363,7 @@ htree_status do_build(htree_ctx *c, bool moments, bool keep_acc = true) {
     launch_gather(c->B, keep_acc, c->stream);
     launch_topology(c->B, moments, c->stream);
     launch_groups(c->B, c->stream);
+    launch_dispatch_orders(c->B, c->stream);
     ev_end(c, 0);
     HIP_OK(hipGetLastError());
     c->tree = true;
@@ -387,6 +392,8 @@ htree_status do_soft(htree_ctx *c) {
     A.acc = c->B.as[c->B.cur];
     const bool pot = (c->p.flags & HTREE_F_POT) != 0;
     A.pot = pot ? c->pot : nullptr;
+    A.order = c->B.sorder;
+    A.wsoft = c->B.wsoft[c->B.cur];
     ev_begin(c, 1);
     launch_soft(A, c->p.hybrid != 0, pot, c->p.precision, c->n_wg, c->stream);
     ev_end(c, 1);
@@ -794,6 +801,7 @@ htree_status htree::ctx_set_state(htree_ctx *c, const double *d_x, int64_t ldx, 
     launch_set_state(d_x, ldx, d_v, d_m, B.x[0], B.v[0], B.m[0], B.perm[0], c->n, c->stream);
     launch_zero_u32((uint32_t *)B.as[0], 3 * c->n, c->stream);
     launch_zero_u32((uint32_t *)B.ah[0], 3 * c->n, c->stream);
+    launch_zero_u32(B.wsoft[0], c->n, c->stream);
     HIP_OK(hipGetLastError());
     c->tree = c->moments = c->boxes = c->have_soft = c->have_hard = c->forces_current = false;
     c->hard_order = false;

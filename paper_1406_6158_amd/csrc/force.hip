@@ -499,6 +499,12 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS<T> &S, uint32_t grp) {
             A.pot[i] = (float)(Q.G * (acc.p - acc.pc));
         }
     }
+    if (A.wsoft && G.act) {
+        // work measure for the next dispatch order: a near entry costs about
+        // two far ones
+        const uint64_t w = (uint64_t)n_pc + n_far + 2ull * n_near;
+        A.wsoft[G.b0 + lane] = w > 0xffffffffull ? 0xffffffffu : (uint32_t)w;
+    }
     if (lane == 0) {
         if (A.gcount) {
             A.gcount[grp] = n_pc;
@@ -515,7 +521,8 @@ __global__ __launch_bounds__(64) void k_soft(ForceArgs A) {
     __shared__ SoftLDS<T> S;
     const uint32_t ng = *A.ng;
     for (uint32_t idx = blockIdx.x; idx < ng; idx += gridDim.x) {
-        const uint32_t grp = sched_group(idx, ng);
+        const uint32_t pos = sched_group(idx, ng);
+        const uint32_t grp = A.order ? A.order[pos] : pos;
         HT_CHECK(grp < ng);
         HT_CHECK(A.gstart[grp + 1] > A.gstart[grp] && A.gstart[grp + 1] - A.gstart[grp] <= 64);
         soft_group<HYBRID, POT, T>(A, S, grp);

@@ -138,6 +138,8 @@ struct BuildBufs {
     uint32_t *perm[2];     // [n] sorted position -> caller index
     float *as[2];          // [3][n] soft acceleration (sorted order)
     float *ah[2];          // [3][n] hard acceleration
+    uint32_t *wsoft[2];    // [n] cost of each particle's soft group in the last launch
+                           // (dispatch estimate for the next groups)
     int cur;
     double4 *src;          // [n] build-frame position and mass
     uint64_t *key[2];      // [n] sort keys (ping-pong)
@@ -178,6 +180,7 @@ struct BuildBufs {
     uint32_t *hkey;        // [n] sort key (descending cost bucket)
     uint32_t *hval;        // [n] group index before the sort
     uint32_t *horder;      // [n] dispatch position -> hard group
+    uint32_t *sorder;      // [n] dispatch position -> soft group
 };
 
 // Host launch wrappers (build.hip).
@@ -190,6 +193,7 @@ void launch_refit(BuildBufs &B, hipStream_t s);
 void refit_sizes(int64_t n, int64_t *m1, int64_t *m2, int64_t *m3);
 void launch_groups(BuildBufs &B, hipStream_t s);
 void launch_hard_order(BuildBufs &B, hipStream_t s);
+void launch_dispatch_orders(BuildBufs &B, hipStream_t s);
 void launch_sys_of(BuildBufs &B, hipStream_t s);
 size_t scan_partials(int64_t n);
 void launch_scan_u32(uint32_t *data, int64_t n, uint32_t *part, uint32_t *total, hipStream_t s);
@@ -218,6 +222,7 @@ struct ForceArgs {
     const Frame *frame;       // [S]
     const uint32_t *order;    // null, or dispatch position -> group (a permutation)
     uint32_t *cost;           // null, or [ng] per-group work measure written by the hard kernel
+    uint32_t *wsoft;          // null, or [n]: each soft group writes its work measure to its sinks
     int64_t n;
     float *acc;               // [3][n] sorted order output
     float *pot;               // [n] or null

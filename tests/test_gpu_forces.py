@@ -116,6 +116,35 @@ def test_forces_deterministic():
         assert np.array_equal(u, w)
 
 
+def test_dispatch_order_invariant():
+    # Groups are dispatched heaviest first by costs measured in earlier
+    # launches (hard: after the first launch over a tree; soft: carried over
+    # to the next build).  Each group writes only its own sinks, so forces,
+    # neighbour counts and tallies must not change with the order.
+    torch, P = need_gpu()
+    n = 20000
+    x, v, m = synth.plummer(n, 61)
+    x, v32, m32, _, _ = as_inputs(x, v, m)
+    R2 = synth.r2_for_neighbours("plummer", n, 48)
+    t = make_tree(P, torch, x, v32, m32, eps=0.01, R1=R2 / 2, R2=R2)
+    t.build_tree()
+    a0 = t.soft_force().cpu().numpy()          # key order (no costs yet)
+    h0, g0 = (u.cpu().numpy() for u in t.hard_force())   # key order, measures
+    t.sync()
+    st0 = t.stats()
+    h1, g1 = (u.cpu().numpy() for u in t.hard_force())   # heaviest first
+    t.build_tree()                              # same positions, carried soft costs
+    a1 = t.soft_force().cpu().numpy()
+    h2, g2 = (u.cpu().numpy() for u in t.hard_force())
+    t.sync()
+    st1 = t.stats()
+    assert np.array_equal(a0, a1)
+    assert np.array_equal(h0, h1) and np.array_equal(g0, g1)
+    assert np.array_equal(h0, h2) and np.array_equal(g0, g2)
+    assert st1["soft_interactions"] == st0["soft_interactions"]
+    assert st1["hard_pairs"] == 2 * st0["hard_pairs"]
+
+
 def test_call_order_errors():
     torch, P = need_gpu()
     (x, v, m), eps, R1, R2 = _wl("plummer4k")
