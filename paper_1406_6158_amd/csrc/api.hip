@@ -187,7 +187,8 @@ void carve(Carver &C, htree_ctx *c) {
         B.ktmp = nullptr;
     }
     B.src = C.take<double4>(n);
-    const int64_t nsort = nnmax > n ? nnmax : n;
+    // the largest sorts: nodes (nnmax) and the dispatch keys of both group kinds (2n)
+    const int64_t nsort = nnmax > 2 * n ? nnmax : 2 * n;
     const int64_t hb = 256 * sort_blocks(nsort);
     B.hist = C.take<uint32_t>(hb + (int64_t)scan_partials(hb));
     B.bbox_part = C.take<double>(6 * B.nchunks);
@@ -197,7 +198,7 @@ void carve(Carver &C, htree_ctx *c) {
     B.leaflev = C.take<int8_t>(n);
     B.nstart = C.take<uint32_t>(n + 1);
     int64_t sp = (int64_t)scan_partials(n + 1);
-    int64_t sp2 = (int64_t)scan_partials(256 * sort_blocks(n));
+    int64_t sp2 = (int64_t)scan_partials(256 * sort_blocks(nsort));
     B.scan_part = C.take<uint32_t>(sp > sp2 ? sp : sp2);
     B.nn = C.take<uint32_t>(4);
     B.pre_key = C.take<uint32_t>(nnmax);
@@ -226,17 +227,20 @@ void carve(Carver &C, htree_ctx *c) {
     B.ng = C.take<uint32_t>(4);
     B.hgstart = C.take<uint32_t>(n + 1);
     B.nhg = C.take<uint32_t>(4);
-    B.hcost = C.take<uint32_t>(n);
-    B.hkey = C.take<uint32_t>(n);
-    B.hval = C.take<uint32_t>(n);
+    B.hcost = C.take<uint32_t>(2 * n);
+    B.hkey = C.take<uint32_t>(2 * n);
+    B.hval = C.take<uint32_t>(2 * n);
     B.horder = C.take<uint32_t>(n);
+    B.ndisp = C.take<uint32_t>(4);
     c->tmp3 = C.take<float>(3 * n);
     c->pot = C.take<float>(n);
     c->ngb = C.take<int32_t>(n);
     c->gcount = C.take<uint32_t>(3 * n);
-    B.wsoft[0] = C.take<uint32_t>(n);
-    B.wsoft[1] = C.take<uint32_t>(n);
-    B.sorder = C.take<uint32_t>(n);
+    for (int k = 0; k < 2; k++) {
+        B.wsoft[k] = C.take<uint32_t>(n);
+        B.whard[k] = C.take<uint32_t>(n);
+    }
+    B.sorder = C.take<uint32_t>(2 * n);
     c->tally = C.take<unsigned long long>(kTallySlots * kTallyStride);
     c->tally_sum = C.take<unsigned long long>(4);
 }
@@ -410,9 +414,10 @@ htree_status do_hard(htree_ctx *c) {
     A.ng = c->B.nhg;
     A.acc = c->B.ah[c->B.cur];
     A.ngb = c->ngb;
-    // the first launch over new groups measures their costs; later launches
-    // (after refits) dispatch the groups heaviest first
-    A.order = c->hard_order ? c->B.horder : nullptr;
+    // groups run heaviest first: the first launch over new groups by the
+    // costs carried from the last build's groups, and it measures their own
+    // costs, which order the later launches (after refits)
+    A.order = c->B.horder;
     A.cost = c->hard_order ? nullptr : c->B.hcost;
     ev_begin(c, 2);
     launch_hard(A, c->n_wg, c->stream);
@@ -802,6 +807,7 @@ htree_status htree::ctx_set_state(htree_ctx *c, const double *d_x, int64_t ldx, 
     launch_zero_u32((uint32_t *)B.as[0], 3 * c->n, c->stream);
     launch_zero_u32((uint32_t *)B.ah[0], 3 * c->n, c->stream);
     launch_zero_u32(B.wsoft[0], c->n, c->stream);
+    launch_zero_u32(B.whard[0], c->n, c->stream);
     HIP_OK(hipGetLastError());
     c->tree = c->moments = c->boxes = c->have_soft = c->have_hard = c->forces_current = false;
     c->hard_order = false;

@@ -410,57 +410,91 @@ void launch_sort(BuildBufs &B, hipStream_t s) {
 // expensive groups of dense regions do not start late and leave a tail of a
 // few long workgroups.  Costs are bucketed at a quarter octave; the stable
 // sort keeps key order inside a bucket.
-// Sort key of a cost: 255 - (quarter-octave bucket), heaviest first.
-__device__ inline uint32_t cost_key(uint32_t c) {
-    uint32_t b = 0;
-    if (c > 0) {
-        const uint32_t e = 31u - (uint32_t)__builtin_clz(c);
-        const uint32_t f = e >= 2 ? (c >> (e - 2)) & 3u : (c << (2 - e)) & 3u;
-        b = 4 * e + f;                      // <= 127
-    }
-    return 255u - b;
+// Quarter-octave bucket of a cost (0 .. 127).
+__device__ inline uint32_t cost_bucket(uint32_t c) {
+    if (c == 0) return 0;
+    const uint32_t e = 31u - (uint32_t)__builtin_clz(c);
+    const uint32_t f = e >= 2 ? (c >> (e - 2)) & 3u : (c << (2 - e)) & 3u;
+    return 4 * e + f;
 }
 
 __global__ __launch_bounds__(256) void k_hard_order_keys(const uint32_t *cost, const uint32_t *nhg,
                                                          uint32_t *key, uint32_t *val) {
     const uint32_t g = blockIdx.x * 256 + threadIdx.x;
     if (g >= *nhg) return;
-    key[g] = cost_key(cost[g]);
+    key[g] = 255u - cost_bucket(cost[g]);
     val[g] = g;
 }
 
-// Estimated cost of each new group: the mean over its sinks of the cost of
-// the group each sink belonged to in the last launch (particles move little
-// between builds).  Before any launch all estimates are 0: key order.  One
-// wavefront per group (at most 64 sinks), four groups per block.
-__global__ __launch_bounds__(256) void k_group_cost_keys(const uint32_t *gstart,
-                                                         const uint32_t *ngp, const uint32_t *wc,
-                                                         uint32_t *key, uint32_t *val) {
-    const uint32_t ng = *ngp;
+// Keys of both kinds of new groups for one sort: soft group g at entry g with
+// key 127 - bucket, hard group h at entry ng + h with key 255 - bucket, so
+// the sorted values hold the soft order in [0, ng) and the hard order in
+// [ng, ng + nhg).  A group's estimate is the mean over its sinks of the cost
+// of the group each sink belonged to in the last launch (particles move
+// little between builds); before any launch all estimates are 0 (key order).
+// One wavefront per group, four per block.
+__global__ __launch_bounds__(256) void k_dispatch_keys(const uint32_t *gstart, const uint32_t *ngp,
+                                                       const uint32_t *ws, const uint32_t *hgstart,
+                                                       const uint32_t *nhgp, const uint32_t *wh,
+                                                       uint32_t *key, uint32_t *val,
+                                                       uint32_t *total) {
+    const uint32_t ng = *ngp, nhg = *nhgp;
     const int lane = __lane_id();
-    for (uint32_t g = blockIdx.x * 4 + (threadIdx.x >> 6); g < ng; g += gridDim.x * 4) {
-        const uint32_t b0 = gstart[g], ns = gstart[g + 1] - b0;
-        uint64_t w = lane < (int)ns ? wc[b0 + lane] : 0u;
-        for (int o = 32; o > 0; o >>= 1) w += __shfl_xor(w, o);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *total = ng + nhg;
+    for (uint32_t g = blockIdx.x * 4 + (threadIdx.x >> 6); g < ng + nhg; g += gridDim.x * 4) {
+        const bool soft = g < ng;
+        const uint32_t k = soft ? g : g - ng;
+        const uint32_t *st = soft ? gstart : hgstart;
+        const uint32_t *w = soft ? ws : wh;
+        const uint32_t b0 = st[k], ns = st[k + 1] - b0;
+        uint64_t sum = lane < (int)ns ? w[b0 + lane] : 0u;
+        for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
         if (lane == 0) {
-            const uint64_t mean = w / ns;
-            key[g] = cost_key(mean > 0xffffffffull ? 0xffffffffu : (uint32_t)mean);
-            val[g] = g;
+            const uint64_t mean = sum / ns;
+            const uint32_t b = cost_bucket(mean > 0xffffffffull ? 0xffffffffu : (uint32_t)mean);
+            key[g] = (soft ? 127u : 255u) - b;
+            val[g] = k;
         }
     }
 }
 
-// Dispatch order of the new soft groups from the carried costs.
-void launch_dispatch_orders(BuildBufs &B, hipStream_t s) {
-    const int64_t n = B.n;
-    const int64_t blocks = (n + 3) / 4 < 2048 ? (n + 3) / 4 : 2048;
-    hipLaunchKernelGGL(k_group_cost_keys, dim3((unsigned)blocks), dim3(256), 0, s, B.gstart, B.ng,
-                       B.wsoft[B.cur], B.hkey, B.hval);
-    radix_pass<uint32_t>(B.hkey, B.hval, B.hcost, B.sorder, B.hist, B.scan_part, B.ng, n, 0, s);
+__global__ __launch_bounds__(256) void k_order_tail(const uint32_t *sorted, const uint32_t *ngp,
+                                                    const uint32_t *nhgp, uint32_t *horder) {
+    const uint32_t k = blockIdx.x * 256 + threadIdx.x;
+    if (k < *nhgp) horder[k] = sorted[*ngp + k];
 }
 
+// The measured cost of each hard group, written to its sinks (carried to the
+// next build's groups by the gather).  One wavefront per group.
+__global__ __launch_bounds__(256) void k_spread_cost(const uint32_t *hgstart, const uint32_t *nhgp,
+                                                     const uint32_t *cost, uint32_t *wh) {
+    const uint32_t nhg = *nhgp;
+    const int lane = __lane_id();
+    for (uint32_t g = blockIdx.x * 4 + (threadIdx.x >> 6); g < nhg; g += gridDim.x * 4) {
+        const uint32_t b0 = hgstart[g], ns = hgstart[g + 1] - b0;
+        if (lane < (int)ns) wh[b0 + lane] = cost[g];
+    }
+}
+
+static unsigned wave_grid(int64_t n) { return (unsigned)((n + 3) / 4 < 2048 ? (n + 3) / 4 : 2048); }
+
+// Dispatch orders of the new soft and hard groups from the carried costs.
+void launch_dispatch_orders(BuildBufs &B, hipStream_t s) {
+    const int64_t n = B.n;
+    hipLaunchKernelGGL(k_dispatch_keys, dim3(wave_grid(2 * n)), dim3(256), 0, s, B.gstart, B.ng,
+                       B.wsoft[B.cur], B.hgstart, B.nhg, B.whard[B.cur], B.hkey, B.hval, B.ndisp);
+    radix_pass<uint32_t>(B.hkey, B.hval, B.hcost, B.sorder, B.hist, B.scan_part, B.ndisp, 2 * n, 0,
+                         s);
+    hipLaunchKernelGGL(k_order_tail, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, B.sorder,
+                       B.ng, B.nhg, B.horder);
+}
+
+// After the first launch over new hard groups: their measured costs go to
+// their sinks, and order the later launches.
 void launch_hard_order(BuildBufs &B, hipStream_t s) {
     const int64_t n = B.n;
+    hipLaunchKernelGGL(k_spread_cost, dim3(wave_grid(n)), dim3(256), 0, s, B.hgstart, B.nhg,
+                       B.hcost, B.whard[B.cur]);
     hipLaunchKernelGGL(k_hard_order_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
                        B.hcost, B.nhg, B.hkey, B.hval);
     radix_pass<uint32_t>(B.hkey, B.hval, B.hcost, B.horder, B.hist, B.scan_part, B.nhg, n, 0, s);
@@ -473,8 +507,8 @@ template <bool ACC>
 __global__ __launch_bounds__(256) void k_gather(
     const uint32_t *idx, int64_t n, const uint32_t *sys_of, const Frame *frames, const double *x0,
     const float *v0, const float *m0, const uint32_t *p0, const float *as0, const float *ah0,
-    const uint32_t *wc0, double *x1, float *v1, float *m1, uint32_t *p1, float *as1, float *ah1,
-    uint32_t *wc1, double4 *src) {
+    const uint32_t *wc0, const uint32_t *wh0, double *x1, float *v1, float *m1, uint32_t *p1,
+    float *as1, float *ah1, uint32_t *wc1, uint32_t *wh1, double4 *src) {
     int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n) return;
     uint32_t o = idx[p];
@@ -493,6 +527,7 @@ __global__ __launch_bounds__(256) void k_gather(
     m1[p] = mm;
     p1[p] = p0[o];
     wc1[p] = wc0[o];
+    wh1[p] = wh0[o];
     src[p] = make_double4(xx[0] - F.lo[0], xx[1] - F.lo[1], xx[2] - F.lo[2], (double)mm);
 }
 
@@ -505,13 +540,13 @@ void launch_gather(BuildBufs &B, bool keep_acc, hipStream_t s) {
     if (keep_acc)
         hipLaunchKernelGGL(k_gather<true>, grid, dim3(256), 0, s, B.idx[0], n, B.sys_of, B.frame,
                            B.x[c], B.v[c], B.m[c], B.perm[c], B.as[c], B.ah[c], B.wsoft[c],
-                           B.x[d], B.v[d], B.m[d], B.perm[d], B.as[d], B.ah[d], B.wsoft[d],
-                           B.src);
+                           B.whard[c], B.x[d], B.v[d], B.m[d], B.perm[d], B.as[d], B.ah[d],
+                           B.wsoft[d], B.whard[d], B.src);
     else
         hipLaunchKernelGGL(k_gather<false>, grid, dim3(256), 0, s, B.idx[0], n, B.sys_of,
                            B.frame, B.x[c], B.v[c], B.m[c], B.perm[c], B.as[c], B.ah[c],
-                           B.wsoft[c], B.x[d], B.v[d], B.m[d], B.perm[d], B.as[d], B.ah[d],
-                           B.wsoft[d], B.src);
+                           B.wsoft[c], B.whard[c], B.x[d], B.v[d], B.m[d], B.perm[d], B.as[d],
+                           B.ah[d], B.wsoft[d], B.whard[d], B.src);
     B.cur = d;
 }
 

@@ -139,7 +139,7 @@ struct BuildBufs {
     float *as[2];          // [3][n] soft acceleration (sorted order)
     float *ah[2];          // [3][n] hard acceleration
     uint32_t *wsoft[2];    // [n] cost of each particle's soft group in the last launch
-                           // (dispatch estimate for the next groups)
+    uint32_t *whard[2];    // [n] and of its hard group (dispatch estimates for new groups)
     int cur;
     double4 *src;          // [n] build-frame position and mass
     uint64_t *key[2];      // [n] sort keys (ping-pong)
@@ -176,11 +176,12 @@ struct BuildBufs {
     uint32_t *hgstart;     // [n+1] hard group start positions (nhg + 1 used)
     uint32_t *nhg;         // device hard group count
     // hard-group dispatch order (measured costs, heaviest first)
-    uint32_t *hcost;       // [n] cost of each hard group in the last launch; sort scratch
-    uint32_t *hkey;        // [n] sort key (descending cost bucket)
-    uint32_t *hval;        // [n] group index before the sort
+    uint32_t *hcost;       // [2n] cost of each hard group in the last launch; sort scratch
+    uint32_t *hkey;        // [2n] sort keys (descending cost buckets)
+    uint32_t *hval;        // [2n] group indices before the sort
     uint32_t *horder;      // [n] dispatch position -> hard group
-    uint32_t *sorder;      // [n] dispatch position -> soft group
+    uint32_t *sorder;      // [2n] dispatch position -> soft group (first ng entries)
+    uint32_t *ndisp;       // device count of the dispatch sort (ng + nhg)
 };
 
 // Host launch wrappers (build.hip).
