@@ -762,10 +762,10 @@ __global__ __launch_bounds__(256) void k_level_pass(Node *node, const double4 *s
 // Refit after a drift (same tree, same sorted order): node boxes directly
 // from their particle ranges, which needs no level order.  Boxes of aligned
 // chunks of 32, 32^2 and 32^3 sorted particles are reduced first; a node's
-// range is then covered greedily by the largest aligned chunks that fit (at
-// most 31 pieces of each size on either side), one lane per node, nodes in
-// pre-order.  Minima
-// and maxima are exact, so the boxes equal those of the level pass.
+// range is then covered by the largest aligned chunks that fit (at most 31
+// pieces of each size on either side), one lane per node, nodes in
+// pre-order.  Minima and maxima are exact, so the boxes equal those of the
+// level pass.
 constexpr int kC1 = 32;
 
 // dst[6][ceil(m / 32)]: boxes of 32 consecutive entries of src (particles
@@ -809,31 +809,66 @@ __global__ __launch_bounds__(256) void k_refit(const Node *node, const uint32_t 
     const uint32_t b = pre2bfs[p];
     const uint32_t f = node[b].first, e = f + node[b].count;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-    auto box = [&](const double *t, int64_t m, int64_t k) {
-        for (int a = 0; a < 3; a++) {
-            lo[a] = fmin(lo[a], t[a * m + k]);
-            hi[a] = fmax(hi[a], t[(3 + a) * m + k]);
+    // [f, e) = singles | 32-chunks | 1024-chunks | 32768-chunks | 1024 | 32 | singles,
+    // each run aligned to its chunk size (min and max are exact, so any cover
+    // gives the same box); every run is a counted loop whose loads are issued
+    // four at a time
+    auto run = [&](const double *t, int64_t m, uint32_t k0, uint32_t k1) {
+        for (uint32_t k = k0; k < k1; k += 4) {
+            double l4[4][3], h4[4][3];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const uint32_t kk = k + j < k1 ? k + j : k;
+                for (int a = 0; a < 3; a++) {
+                    l4[j][a] = t[a * m + kk];
+                    h4[j][a] = t[(3 + a) * m + kk];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                for (int a = 0; a < 3; a++) {
+                    lo[a] = fmin(lo[a], l4[j][a]);
+                    hi[a] = fmax(hi[a], h4[j][a]);
+                }
+        }
+    };
+    auto singles = [&](uint32_t i0, uint32_t i1) {
+        for (uint32_t i = i0; i < i1; i += 4) {
+            double v4[4][3];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const uint32_t ii = i + j < i1 ? i + j : i;
+                for (int a = 0; a < 3; a++) v4[j][a] = x[a * n + ii];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; j++)
+                for (int a = 0; a < 3; a++) {
+                    lo[a] = fmin(lo[a], v4[j][a]);
+                    hi[a] = fmax(hi[a], v4[j][a]);
+                }
         }
     };
     constexpr uint32_t S1 = kC1, S2 = kC1 * kC1, S3 = kC1 * kC1 * kC1;
-    uint32_t i = f;
-    while (i < e) {
-        if (i % S3 == 0 && e - i >= S3) {
-            box(c3, m3, i / S3);
-            i += S3;
-        } else if (i % S2 == 0 && e - i >= S2) {
-            box(c2, m2, i / S2);
-            i += S2;
-        } else if (i % S1 == 0 && e - i >= S1) {
-            box(c1, m1, i / S1);
-            i += S1;
+    const uint32_t a1 = (f + S1 - 1) / S1 * S1, b1 = e / S1 * S1;
+    if (a1 >= b1) {
+        singles(f, e);
+    } else {
+        singles(f, a1);
+        singles(b1, e);
+        const uint32_t a2 = (a1 + S2 - 1) / S2 * S2, b2 = b1 / S2 * S2;
+        if (a2 >= b2) {
+            run(c1, m1, a1 / S1, b1 / S1);
         } else {
-            for (int a = 0; a < 3; a++) {
-                const double v = x[a * n + i];
-                lo[a] = fmin(lo[a], v);
-                hi[a] = fmax(hi[a], v);
+            run(c1, m1, a1 / S1, a2 / S1);
+            run(c1, m1, b2 / S1, b1 / S1);
+            const uint32_t a3 = (a2 + S3 - 1) / S3 * S3, b3 = b2 / S3 * S3;
+            if (a3 >= b3) {
+                run(c2, m2, a2 / S2, b2 / S2);
+            } else {
+                run(c2, m2, a2 / S2, a3 / S2);
+                run(c2, m2, b3 / S2, b2 / S2);
+                run(c3, m3, a3 / S3, b3 / S3);
             }
-            i += 1;
         }
     }
     for (int a = 0; a < 3; a++) {
