@@ -89,24 +89,37 @@ __device__ inline T wave_max(T v) {
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
     return v;
 }
-__device__ inline uint32_t wave_max_u32(uint32_t v) {
-    for (int o = 32; o > 0; o >>= 1) {
-        const uint32_t t = (uint32_t)__shfl_xor(v, o);
-        v = t > v ? t : v;
-    }
-    return v;
+// Inclusive scans over the 64 lanes with DPP moves (no LDS round trips):
+// shifts by 1, 2, 4, 8 inside each row of 16 lanes, then the row totals by
+// the GFX9 row broadcasts (lane 15 into rows 1 and 3, lane 31 into rows 2
+// and 3).  Lanes a move does not write, or whose source lies outside the
+// row, take 0 (the identity of + and of max on unsigned values).  All 64
+// lanes must be active.
+template <int CTRL, int ROWS>
+__device__ inline uint32_t dpp_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
 }
 __device__ inline uint32_t wave_incl_scan(uint32_t v) {
-    const int lane = __lane_id();
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t t = __shfl_up(v, o);
-        if (lane >= o) v += t;
-    }
+    v += dpp_u32<0x111, 0xf>(v);
+    v += dpp_u32<0x112, 0xf>(v);
+    v += dpp_u32<0x114, 0xf>(v);
+    v += dpp_u32<0x118, 0xf>(v);
+    v += dpp_u32<0x142, 0xa>(v);
+    v += dpp_u32<0x143, 0xc>(v);
     return v;
 }
 __device__ inline uint32_t wave_sum(uint32_t v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    return (uint32_t)__builtin_amdgcn_readlane(wave_incl_scan(v), 63);
+}
+__device__ inline uint32_t max_u32(uint32_t a, uint32_t b) { return a > b ? a : b; }
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+    v = max_u32(v, dpp_u32<0x111, 0xf>(v));
+    v = max_u32(v, dpp_u32<0x112, 0xf>(v));
+    v = max_u32(v, dpp_u32<0x114, 0xf>(v));
+    v = max_u32(v, dpp_u32<0x118, 0xf>(v));
+    v = max_u32(v, dpp_u32<0x142, 0xa>(v));
+    v = max_u32(v, dpp_u32<0x143, 0xc>(v));
+    return (uint32_t)__builtin_amdgcn_readlane(v, 63);
 }
 
 // Sticky device status bits.
