@@ -276,7 +276,7 @@ __device__ inline uint32_t take_items(uint32_t *first, uint32_t *cnt, int &nr, i
     HT_CHECK(__shfl(inc, r - 1) >= (uint32_t)want);
     uint64_t full = __ballot(lane < r && inc <= (uint32_t)want);
     int nfull = __popcll(full);
-    uint32_t used = nfull ? __shfl(inc, nfull - 1) : 0u;
+    uint32_t used = nfull ? (uint32_t)__builtin_amdgcn_readlane(inc, nfull - 1) : 0u;
     __syncthreads();
     if (lane == 0 && (uint32_t)want > used) cnt[O.slot(nr - 1 - nfull)] -= (uint32_t)want - used;
     nr -= nfull;

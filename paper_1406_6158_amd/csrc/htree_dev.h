@@ -79,16 +79,6 @@ static_assert(sizeof(Node) == 96, "node record layout");
 // ---------------------------------------------------------------------------
 __device__ inline uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 
-template <typename T>
-__device__ inline T wave_min(T v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-    return v;
-}
-template <typename T>
-__device__ inline T wave_max(T v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
-    return v;
-}
 // Inclusive scans over the 64 lanes with DPP moves (no LDS round trips):
 // shifts by 1, 2, 4, 8 inside each row of 16 lanes, then the row totals by
 // the GFX9 row broadcasts (lane 15 into rows 1 and 3, lane 31 into rows 2
@@ -112,6 +102,45 @@ __device__ inline uint32_t wave_sum(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readlane(wave_incl_scan(v), 63);
 }
 __device__ inline uint32_t max_u32(uint32_t a, uint32_t b) { return a > b ? a : b; }
+// FP64 minimum / maximum over the 64 lanes, returned in every lane: the same
+// DPP pattern on both halves of the value, with +inf / -inf for lanes a
+// move does not write.  All 64 lanes must be active.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_f64(double v, double idle) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v), o = (uint64_t)__double_as_longlong(idle);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)o, (int)(uint32_t)b,
+                                                              CTRL, ROWS, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp((int)(uint32_t)(o >> 32),
+                                                              (int)(uint32_t)(b >> 32), CTRL,
+                                                              ROWS, 0xf, false);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ inline double lane63_f64(double v) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), 63);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ inline double wave_min(double v) {
+    const double e = INFINITY;
+    v = fmin(v, dpp_f64<0x111, 0xf>(v, e));
+    v = fmin(v, dpp_f64<0x112, 0xf>(v, e));
+    v = fmin(v, dpp_f64<0x114, 0xf>(v, e));
+    v = fmin(v, dpp_f64<0x118, 0xf>(v, e));
+    v = fmin(v, dpp_f64<0x142, 0xa>(v, e));
+    v = fmin(v, dpp_f64<0x143, 0xc>(v, e));
+    return lane63_f64(v);
+}
+__device__ inline double wave_max(double v) {
+    const double e = -INFINITY;
+    v = fmax(v, dpp_f64<0x111, 0xf>(v, e));
+    v = fmax(v, dpp_f64<0x112, 0xf>(v, e));
+    v = fmax(v, dpp_f64<0x114, 0xf>(v, e));
+    v = fmax(v, dpp_f64<0x118, 0xf>(v, e));
+    v = fmax(v, dpp_f64<0x142, 0xa>(v, e));
+    v = fmax(v, dpp_f64<0x143, 0xc>(v, e));
+    return lane63_f64(v);
+}
 __device__ inline uint32_t wave_max_u32(uint32_t v) {
     v = max_u32(v, dpp_u32<0x111, 0xf>(v));
     v = max_u32(v, dpp_u32<0x112, 0xf>(v));
