@@ -259,17 +259,20 @@ __device__ inline uint32_t take_items(uint32_t *first, uint32_t *cnt, int &nr, i
     int r = nr < 64 ? nr : 64;
     uint32_t ck = lane < r ? cnt[O.slot(nr - 1 - lane)] : 0u;
     uint32_t inc = wave_incl_scan(ck);
-    scan[lane] = inc;
+    const uint32_t exc = inc - ck;
+    // item j belongs to the last range starting at or before j: each range
+    // marks its start (start << 8 | index + 1), a running maximum over the
+    // lanes carries the mark to the items after it
+    scan[lane] = 0u;
     __syncthreads();
+    if (lane < r && exc < 64u) scan[exc] = (exc << 8) | (uint32_t)(lane + 1);
+    __syncthreads();
+    const uint32_t own = wave_incl_max(scan[lane]);
     uint32_t item = 0;
     if (lane < want) {
-        int lo = 0, hi = r - 1;
-        while (lo < hi) {
-            int mid = (lo + hi) >> 1;
-            if (scan[mid] > (uint32_t)lane) hi = mid; else lo = mid + 1;
-        }
-        uint32_t prev = lo ? scan[lo - 1] : 0u;
-        const int sl = O.slot(nr - 1 - lo);
+        const int k = (int)(own & 255u) - 1;
+        const uint32_t prev = own >> 8;
+        const int sl = O.slot(nr - 1 - k);
         uint32_t f = first[sl], c = cnt[sl];
         item = f + c - 1u - ((uint32_t)lane - prev);
     }

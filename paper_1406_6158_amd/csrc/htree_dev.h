@@ -141,14 +141,17 @@ __device__ inline double wave_max(double v) {
     v = fmax(v, dpp_f64<0x143, 0xc>(v, e));
     return lane63_f64(v);
 }
-__device__ inline uint32_t wave_max_u32(uint32_t v) {
+__device__ inline uint32_t wave_incl_max(uint32_t v) {
     v = max_u32(v, dpp_u32<0x111, 0xf>(v));
     v = max_u32(v, dpp_u32<0x112, 0xf>(v));
     v = max_u32(v, dpp_u32<0x114, 0xf>(v));
     v = max_u32(v, dpp_u32<0x118, 0xf>(v));
     v = max_u32(v, dpp_u32<0x142, 0xa>(v));
     v = max_u32(v, dpp_u32<0x143, 0xc>(v));
-    return (uint32_t)__builtin_amdgcn_readlane(v, 63);
+    return v;
+}
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_readlane(wave_incl_max(v), 63);
 }
 
 // Sticky device status bits.
