@@ -61,8 +61,8 @@ PEAK_FP32_PACKED = 157.3
 # summary with commands is profiles/counters_plummer1m_step.txt).  Valid only
 # for the kernel source it was measured on: reported as null once force.hip or
 # htree_dev.h differ from that source.
-SOFT_TRAFFIC = {"bytes": 1919.1e6, "source_hash": "44ce320e2fa17733"}
-HARD_TRAFFIC = {"bytes": 1871.4e6, "source_hash": "44ce320e2fa17733"}
+SOFT_TRAFFIC = {"bytes": 1805.9e6, "source_hash": "9338695e88294fb1"}
+HARD_TRAFFIC = {"bytes": 1954.7e6, "source_hash": "9338695e88294fb1"}
 
 
 def _kernel_source_hash():
