@@ -22,7 +22,9 @@
 //
 // Groups are dealt to workgroups by the hardware dispatcher (see sched_group):
 // one workgroup per group for the expected group count, a grid-stride loop
-// beyond it.
+// beyond it.  Work item positions map to groups through a dispatch order
+// (heaviest estimated cost first, built by the library between launches), so
+// that expensive groups do not start last and leave a tail.
 //
 // Hard force (section II.C, eq. 10): per group, a walk that opens every node
 // whose box (the bounding box of its particles' master positions, kept
