@@ -2,8 +2,9 @@
 
 One step = one soft step of the two-timestep leapfrog on the N = 2^20
 Plummer sphere (eps = 0.01, theta = 0.5, cutoff for ~64 neighbours,
-R1 = R2/2, 4 hard substeps of 1/64): four tree builds, one soft force, four
-hard forces and the kicks and drifts, all inside libhtree on the GPU.
+R1 = R2/2, 4 hard substeps of 1/64): one tree build, three refits of the
+node boxes, one soft force, four hard forces and the kicks and drifts, all
+inside libhtree on the GPU.
 
 Prints one JSON line.  ``value`` is the whole-job interaction rate: (soft
 interactions + accepted hard pairs) per step divided by the step time.  The
@@ -12,7 +13,9 @@ FP64 pair tests and pair forces), ``roofline_interaction`` the soft walk +
 FP32 interaction kernel; both are timed with HIP events recorded by the
 library on its stream around each launch over the timed steps.
 ``cpu_baseline`` times the FP64 oracle on the host cores on a bounded sample
-of the same workload.
+of the same workload, and compares the library's forces of the benchmarked
+configuration (same positions, same launch configuration) with the
+oracle's on that sample: ``parity`` repeats the p99 errors.
 
 Two further sections run after the timed steps and are reported beside
 them: ``ensemble`` (512 independent Plummer clusters, N log-uniform in
@@ -43,12 +46,14 @@ if ROOT not in sys.path:
 # the (1 - K) polynomial and weight (7) = 32.
 FLOPS_FAR = 19
 FLOPS_NEAR = 32
-# Algorithmic FP64 flops of the hard kernel: a candidate pair test is 3 sub,
-# 1 mul, 2 fma (r^2) = 8; an accepted pair adds r^2 + eps^2 (1), two
-# 1/sqrt (seed 1 + Newton step 5 each, the second times r^2: +1), K(r) (10),
-# the force factor (4) and 3 fma (6), with its offsets and r^2 again (8) = 42.
+# Algorithmic FP64 flops of the hard force (section II.C eqs. 7-10): a
+# candidate pair test is 3 sub, 1 mul, 2 fma (r^2) = 8; an accepted pair adds
+# r = sqrt(r^2) (1), r^2 + eps^2 (1), its inverse 3/2 power (rsqrt and two
+# mul, 3), K(r) (Y: sub and mul, Y^2, two fma, Y^6 by two mul, product: 10),
+# the factor m K / (r^2 + eps^2)^{3/2} (2) and the three fma of the sum (6)
+# = 23, whatever instructions an implementation spends on them.
 FLOPS_HARD_TEST = 8
-FLOPS_HARD_PAIR = 42
+FLOPS_HARD_PAIR = 23
 PEAK_FP64 = 78.6
 # MI355X vector peaks derived from the unit counts: 256 CUs x 4 SIMD x 16 lanes
 # x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s for non-packed FP32 (the build
@@ -80,9 +85,12 @@ def _kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(wl, x, m64, seconds_hint=20.0):
+def cpu_baseline(wl, x, m64, gpu=None, seconds_hint=20.0):
     """Oracle soft force (tree walk + FP64 interactions) over a sample of
-    sink groups of the same tree, on all host threads."""
+    sink groups of the same tree, on all host threads.  With ``gpu`` (the
+    library's soft and hard forces and neighbour counts of the benchmarked
+    configuration at the same positions, caller order), also the parity of
+    those results against the oracle on the sampled groups and sinks."""
     import numpy as np
 
     import oracle
@@ -100,15 +108,38 @@ def cpu_baseline(wl, x, m64, seconds_hint=20.0):
     k2 = int(min(ng, max(k, k * seconds_hint / max(dt, 1e-3))))
     groups = synth.sample_indices(ng, k2, 8)
     t0 = time.perf_counter()
-    _, _, inter = T.soft(1.0, wl.eps, wl.R1, wl.R2, 1, groups=groups)
+    o_soft, _, inter = T.soft(1.0, wl.eps, wl.R1, wl.R2, 1, groups=groups)
     dt = time.perf_counter() - t0
     # the other phases, for context: the hard force (direct neighbour sums) on
     # a sample of sinks, and the direct force on a sample, both scaled to N
     n = x.shape[1]
     hs = synth.sample_indices(n, 4096, 9)
     t0 = time.perf_counter()
-    oracle.split_direct(x, m64, 1.0, wl.eps, wl.R1, wl.R2, sinks=hs, soft=False)
+    o_hard, _, o_ngb = oracle.split_direct(x, m64, 1.0, wl.eps, wl.R1, wl.R2, sinks=hs, soft=False)
     t_hard = (time.perf_counter() - t0) * n / len(hs)
+    parity = None
+    if gpu is not None:
+        perm, _, _ = T.sorted()
+        st = T.group_starts()
+        sinks = np.concatenate([perm[st[k]:st[k + 1]] for k in groups])
+
+        def rel(a, ref):
+            return np.linalg.norm(a - ref, axis=0) / np.linalg.norm(ref, axis=0)
+
+        es = rel(gpu["soft"][:, sinks], o_soft[:, sinks])
+        hm = o_ngb > 0
+        eh = rel(gpu["hard"][:, hs], o_hard)[hm]
+        parity = {
+            "reference": "FP64 oracle on the same tree and lists (soft: every sink of the %d "
+                         "sampled groups; hard: %d sampled sinks, brute-force neighbour sets)"
+                         % (len(groups), len(hs)),
+            "soft_p50": float(np.percentile(es, 50)), "soft_p99": float(np.percentile(es, 99)),
+            "soft_max": float(es.max()), "soft_sinks": int(sinks.size),
+            "hard_p50": float(np.percentile(eh, 50)), "hard_p99": float(np.percentile(eh, 99)),
+            "hard_max": float(eh.max()),
+            "hard_ngb_exact": bool(np.array_equal(gpu["ngb"][hs], o_ngb)),
+            "tolerance_p99": 1e-5,
+        }
     ds = synth.sample_indices(n, 1024, 10)
     t0 = time.perf_counter()
     oracle.direct(x, m64, 1.0, wl.eps, sinks=ds)
@@ -130,7 +161,8 @@ def cpu_baseline(wl, x, m64, seconds_hint=20.0):
             "phases_s": {"tree_build": t_build,
                          "soft_all_groups_extrapolated": dt * ng / k2,
                          "hard_extrapolated_from_4096_sinks": t_hard,
-                         "direct_extrapolated_from_1024_sinks": t_direct}}
+                         "direct_extrapolated_from_1024_sinks": t_direct},
+            "parity": parity}
 
 
 def _log(msg):
@@ -449,6 +481,7 @@ def main():
         print("bench: warmup step %d done" % k, file=sys.stderr, flush=True)
     t.stats()                                # reset counters and event timings
     torch.cuda.synchronize()
+    gpu_forces = None
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
     t0 = time.perf_counter()
@@ -520,6 +553,19 @@ def main():
         "cpu_baseline": None,
     }
     t.close()
+    if not args.no_cpu_baseline:
+        # the benchmarked configuration's forces at the initial positions, for
+        # the parity statement of the CPU-baseline leg
+        tp = P.HTree(wl.n, params, device=dev)
+        tp.set_state(torch.from_numpy(x), torch.from_numpy(v32), torch.from_numpy(m32))
+        tp.build_tree()
+        a_s = tp.soft_force()
+        a_h, ngb = tp.hard_force()
+        tp.sync()
+        gpu_forces = {"soft": a_s.cpu().numpy().astype(np.float64),
+                      "hard": a_h.cpu().numpy().astype(np.float64),
+                      "ngb": ngb.cpu().numpy().astype(np.int64)}
+        tp.close()
     if not args.no_comparator:
         hard_call = st["ms_hard"] / max(st["calls_hard"], 1)
         line["comparator"] = comparator(P, torch, wl, x, v32, m32, ms_step, hard_call,
@@ -534,7 +580,10 @@ def main():
         ]
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(wl, x, m32.astype(np.float64))
+        line["cpu_baseline"] = cpu_baseline(wl, x, m32.astype(np.float64), gpu=gpu_forces)
+        par = line["cpu_baseline"]["parity"]
+        line["parity"] = {k: par[k] for k in ("soft_p99", "hard_p99", "hard_ngb_exact",
+                                              "tolerance_p99")}
     print(json.dumps(line), flush=True)
 
 

@@ -69,6 +69,10 @@ typedef struct {
                           /* 1 FP64 (results are still stored as FP32); the hard    */
                           /* force always sums its pair terms in FP64               */
     int32_t flags;        /* HTREE_F_*                                               */
+    int32_t group_cell;   /* soft sink groups: the chunking cells are the cells of   */
+                          /* at most group_cell * group_size particles whose parent */
+                          /* holds more, and the leaves whose parent holds more;    */
+                          /* each is cut into chunks of group_size (1..4096)        */
 } htree_params;
 
 typedef struct {
@@ -86,7 +90,8 @@ typedef struct {
 typedef struct htree_ctx htree_ctx;
 
 /* Defaults: G = 1, eps = 0.01, theta = 0.5, R1 = 0.05, R2 = 0.1, dt_soft = 1/16,
- * n_sub = 4, hybrid = 1, n_crit = 16, group_size = 64, precision = 0, flags = 0. */
+ * n_sub = 4, hybrid = 1, n_crit = 16, group_size = 64, precision = 0, flags = 0,
+ * group_cell = 16. */
 void htree_default_params(htree_params *p);
 
 /* Exact number of workspace bytes a context for n particles needs (0 if the
@@ -264,13 +269,17 @@ htree_status htree_server_create(htree_server **srv, void *d_arena, size_t arena
 
 /* Queues one solve: d_x holds the x, y and z rows of the positions, ldx >= n
  * doubles apart (the first n of each row are used); d_m [n] f32 masses.  Both
- * must stay valid until the request has finished.  HTREE_F_TIMING is
- * rejected.  Writes the request id (> 0).  EINVAL for bad parameters, ENOMEM
- * if the footprint exceeds the whole arena (never admissible).  Admits what
- * it can before returning. */
+ * must stay valid until the request has finished.  hip_input_stream is the
+ * stream (hipStream_t, NULL: the null stream) on which the work that writes
+ * d_x and d_m was enqueued: the solve reads them only after everything
+ * enqueued on that stream before this call (an event recorded there now, and
+ * waited for on the solve's stream).  HTREE_F_TIMING is rejected.  Writes the
+ * request id (> 0).  EINVAL for bad parameters, ENOMEM if the footprint
+ * exceeds the whole arena (never admissible), EDEVICE.  Admits what it can
+ * before returning. */
 htree_status htree_server_submit(htree_server *srv, const htree_params *p, int64_t n,
                                  const double *d_x, int64_t ldx, const float *d_m,
-                                 int64_t *id);
+                                 void *hip_input_stream, int64_t *id);
 
 /* Non-blocking: detects finished solves, admits queued ones, and writes up to
  * max_done ids of requests that finished (or failed) since they were last

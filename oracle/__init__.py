@@ -62,14 +62,14 @@ def lib():
         L.orc_tree_sorted.argtypes = [_p, _p, _p, _p]
         L.orc_tree_nodes.argtypes = [_p] * 11
         L.orc_tree_groups.restype = _i64
-        L.orc_tree_groups.argtypes = [_p, _i32]
+        L.orc_tree_groups.argtypes = [_p, _i32, _i32]
         L.orc_tree_group_starts.argtypes = [_p, _p]
         L.orc_walk_counts.argtypes = [_p, _f64, _i32, _p, _p, _p]
         L.orc_walk_group.argtypes = [_p, _i64, _f64, _i32, _i64, _p, _p, _p, _p]
         L.orc_soft.restype = _i64
         L.orc_soft.argtypes = [_p, _f64, _f64, _f64, _f64, _i32, _i64, _p, _p, _p]
         L.orc_step.argtypes = [_i64, _p, _p, _p, _f64, _f64, _f64, _f64, _f64, _i32, _i32,
-                               _i32, _f64, _i32, _i32]
+                               _i32, _i32, _f64, _i32, _i32]
         _lib = L
     return _lib
 
@@ -138,7 +138,7 @@ def energy(x, v, m, G=1.0, eps=0.0):
 class Tree:
     """The oracle's octree over a particle set (built on construction)."""
 
-    def __init__(self, x, m, n_crit=16, theta=0.5, group=64):
+    def __init__(self, x, m, n_crit=16, theta=0.5, group=64, chunk=16):
         self.x = _f64c(x)
         self.m = _f64c(m)
         self.n = self.x.shape[1]
@@ -149,7 +149,8 @@ class Tree:
         if not self._h:
             raise ValueError("oracle tree build rejected its arguments")
         self.g = int(group)
-        self.ngroups = int(lib().orc_tree_groups(self._h, self.g))
+        self.chunk = int(chunk)
+        self.ngroups = int(lib().orc_tree_groups(self._h, self.g, self.chunk))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -221,11 +222,12 @@ class Tree:
         return acc, pot, int(inter)
 
 
-def step(x, v, m, G, eps, theta, R1, R2, n_crit, g, hybrid, dt_soft, n_sub, n_soft):
-    """Nested kick-drift-kick; returns new (x, v) (inputs are not modified)."""
+def step(x, v, m, G, eps, theta, R1, R2, n_crit, g, hybrid, dt_soft, n_sub, n_soft, chunk=16):
+    """Nested kick-drift-kick; returns new (x, v) (inputs are not modified).
+    ``g`` and ``chunk`` set the sink groups (group size, chunking limit chunk * g)."""
     x = _f64c(x).copy()
     v = _f64c(v).copy()
     m = _f64c(m)
     lib().orc_step(x.shape[1], _ptr(x), _ptr(v), _ptr(m), G, eps, theta, R1, R2, n_crit, g,
-                   int(hybrid), dt_soft, n_sub, n_soft)
+                   int(chunk), int(hybrid), dt_soft, n_sub, n_soft)
     return x, v

@@ -507,30 +507,30 @@ static void gpush(orc_tree *T, int64_t start)
 
 /*
  * Groups of at most g sorted particles (reading of section III.A.2: the
- * sinks of a group are consecutive in key order and lie in one cell).  The
- * chunking cells are the cells with at most 16 g particles whose parent holds
- * more (the root if it holds at most 16 g), and the leaves whose parent holds
- * more: each is cut into consecutive chunks of g particles, the last one
- * shorter.  A cell of at most g particles is therefore one group.
+ * sinks of a group are consecutive in key order and lie in one cell).  With
+ * the chunking limit L = cells * g, the chunking cells are the cells with at
+ * most L particles whose parent holds more (the root if it holds at most L),
+ * and the leaves whose parent holds more: each is cut into consecutive
+ * chunks of g particles, the last one shorter.  A cell of at most g particles
+ * is therefore one group.
  */
-#define ORC_CHUNK_CELL 16
-
-static void groups_rec(orc_tree *T, int64_t id, int64_t g)
+static void groups_rec(orc_tree *T, int64_t id, int64_t g, int64_t lim)
 {
     const onode *c = &T->nd[id];
-    if (c->count <= ORC_CHUNK_CELL * g || c->nchild == 0) {
+    if (c->count <= lim || c->nchild == 0) {
         for (int64_t s = c->first; s < c->first + c->count; s += g) gpush(T, s);
         return;
     }
-    for (int k = 0; k < c->nchild; k++) groups_rec(T, c->child[k], g);
+    for (int k = 0; k < c->nchild; k++) groups_rec(T, c->child[k], g, lim);
 }
 
-/* Builds the sink groups for group size g; returns their number. */
-int64_t orc_tree_groups(orc_tree *T, int32_t g)
+/* Builds the sink groups for group size g >= 1 and chunking limit
+ * cells * g (cells >= 1); returns their number. */
+int64_t orc_tree_groups(orc_tree *T, int32_t g, int32_t cells)
 {
     T->ng = 0;
     T->g = g;
-    groups_rec(T, 0, g);
+    groups_rec(T, 0, g, (int64_t)cells * g);
     T->gstart[T->ng] = T->n;
     return T->ng;
 }
@@ -752,11 +752,11 @@ int64_t orc_soft(const orc_tree *T, double G, double eps, double R1, double R2,
 /* Full force used by the integrator: soft tree force plus the direct hard
  * force (hybrid), or the plain tree force. Writes a_s and a_h (caller order). */
 static void forces(int64_t n, const double *x, const double *m, double G, double eps,
-                   double theta, double R1, double R2, int32_t n_crit, int32_t g, int32_t hybrid,
-                   double *a_s, double *a_h)
+                   double theta, double R1, double R2, int32_t n_crit, int32_t g, int32_t cells,
+                   int32_t hybrid, double *a_s, double *a_h)
 {
     orc_tree *T = orc_tree_build(n, x, m, n_crit, theta);
-    orc_tree_groups(T, g);
+    orc_tree_groups(T, g, cells);
     orc_soft(T, G, eps, R1, R2, hybrid, 0, NULL, a_s, NULL);
     orc_tree_free(T);
     if (hybrid)
@@ -780,20 +780,21 @@ static void forces(int64_t n, const double *x, const double *m, double G, double
  * updated in place (caller order).
  */
 void orc_step(int64_t n, double *x, double *v, const double *m, double G, double eps,
-              double theta, double R1, double R2, int32_t n_crit, int32_t g, int32_t hybrid,
+              double theta, double R1, double R2, int32_t n_crit, int32_t g, int32_t cells,
+              int32_t hybrid,
               double dt_soft, int32_t n_sub, int32_t n_soft)
 {
     size_t s3 = sizeof(double) * 3 * (size_t)n;
     double *a_s = (double *)malloc(s3), *a_h = (double *)malloc(s3);
     double dt_h = dt_soft / n_sub;
-    forces(n, x, m, G, eps, theta, R1, R2, n_crit, g, hybrid, a_s, a_h);
+    forces(n, x, m, G, eps, theta, R1, R2, n_crit, g, cells, hybrid, a_s, a_h);
     for (int32_t s = 0; s < n_soft; s++) {
         for (int64_t k = 0; k < 3 * n; k++) v[k] += 0.5 * dt_soft * a_s[k];
         for (int32_t h = 0; h < n_sub; h++) {
             for (int64_t k = 0; k < 3 * n; k++) v[k] += 0.5 * dt_h * a_h[k];
             for (int64_t k = 0; k < 3 * n; k++) x[k] += dt_h * v[k];
             if (h == n_sub - 1) {
-                forces(n, x, m, G, eps, theta, R1, R2, n_crit, g, hybrid, a_s, a_h);
+                forces(n, x, m, G, eps, theta, R1, R2, n_crit, g, cells, hybrid, a_s, a_h);
             } else if (hybrid) {
                 orc_split_direct(n, x, m, G, eps, R1, R2, n, NULL, a_h, NULL, NULL);
             }

@@ -34,7 +34,8 @@ class Params(C.Structure):
     _fields_ = [("G", C.c_double), ("eps", C.c_double), ("theta", C.c_double),
                 ("R1", C.c_double), ("R2", C.c_double), ("dt_soft", C.c_double),
                 ("n_sub", C.c_int32), ("hybrid", C.c_int32), ("n_crit", C.c_int32),
-                ("group_size", C.c_int32), ("precision", C.c_int32), ("flags", C.c_int32)]
+                ("group_size", C.c_int32), ("precision", C.c_int32), ("flags", C.c_int32),
+                ("group_cell", C.c_int32)]
 
 
 class Counters(C.Structure):
@@ -120,7 +121,7 @@ def lib() -> C.CDLL:
     L.htree_solve_footprint.argtypes = [C.POINTER(Params), C.c_int64]
     L.htree_solve_footprint.restype = C.c_size_t
     L.htree_server_create.argtypes = [C.POINTER(_p), _p, C.c_size_t, _p, C.c_int32, C.c_int32]
-    L.htree_server_submit.argtypes = [_p, C.POINTER(Params), C.c_int64, _p, C.c_int64, _p,
+    L.htree_server_submit.argtypes = [_p, C.POINTER(Params), C.c_int64, _p, C.c_int64, _p, _p,
                                       C.POINTER(C.c_int64)]
     L.htree_server_poll.argtypes = [_p, _p, C.c_int32, C.POINTER(C.c_int32)]
     L.htree_server_result.argtypes = [_p, C.c_int64, C.POINTER(RequestInfo), C.POINTER(_p),

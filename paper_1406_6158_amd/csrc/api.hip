@@ -70,6 +70,8 @@ htree_status validate_one(const htree_params *p, int64_t n) {
     if (p->precision != 0 && p->precision != 1)
         return fail(HTREE_EINVAL, "precision must be 0 (FP32) or 1 (FP64 interactions)");
     if (p->flags & ~(HTREE_F_POT | HTREE_F_TIMING)) return fail(HTREE_EINVAL, "unknown flags");
+    if (p->group_cell < 1 || p->group_cell > 4096)
+        return fail(HTREE_EINVAL, "group_cell must be in [1, 4096]");
     return HTREE_OK;
 }
 
@@ -285,6 +287,7 @@ htree_status upload_tables(htree_ctx *c) {
         y.c1 = (uint32_t)chunks.size();
         y.n_crit = (uint32_t)q.n_crit;
         y.g = (uint32_t)q.group_size;
+        y.gcell = (uint32_t)q.group_cell;
         y.invth2 = 1.0 / (q.theta * q.theta);
         y.R2 = q.hybrid ? q.R2 : 0.0;
         SysF &f = sysf[s];
@@ -473,6 +476,7 @@ void htree_default_params(htree_params *p) {
     p->group_size = 64;
     p->precision = 0;
     p->flags = 0;
+    p->group_cell = 16;
 }
 
 size_t htree_batch_workspace_bytes(const htree_params *p, const int64_t *n, int32_t S) {

@@ -954,23 +954,22 @@ void launch_topology(BuildBufs &B, bool moments, hipStream_t s) {
 
 // ---------------------------------------------------------------------------
 // sink groups.  Soft groups (the same rule as the tree contract; g is the
-// system's group size): the chunking cells -- cells of at most 16 g particles
-// whose parent holds more (the root if it is that small), and leaves whose
-// parent holds more -- are cut into consecutive chunks of g.  Hard groups
+// system's group size, L = gcell * g its chunking limit): the chunking cells
+// -- cells of at most L particles whose parent holds more (the root if it is
+// that small), and leaves whose parent holds more -- are cut into
+// consecutive chunks of g.  Hard groups
 // (the hard kernel's own table; any partition gives the same neighbour sets):
 // a cell with at most g particles is a group; a bigger cell is split into its
 // children; where all children are small, consecutive children are packed
 // while the total stays <= g; a bigger leaf is cut into chunks of g.  Each
 // node marks the group starts it owns; a scan turns the marks into a table.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kChunkCell = 16;
-
 __global__ __launch_bounds__(256) void k_soft_group_marks(const Node *node, const uint32_t *nn_dev,
                                                           const Sys *sys, uint32_t *flag) {
     uint32_t b = blockIdx.x * 256 + threadIdx.x;
     if (b >= *nn_dev) return;
     const Node &N = node[b];
-    const uint32_t g = sys[N.sys].g, lim = kChunkCell * g;
+    const uint32_t g = sys[N.sys].g, lim = sys[N.sys].gcell * g;
     const uint32_t count = N.count, nch = N.meta & 255u;
     if (count > lim && nch != 0) return;                        // split further
     if ((N.meta >> 8) != 0 && node[N.parent].count <= lim) return;   // inside a chunking cell

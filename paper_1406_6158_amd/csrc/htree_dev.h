@@ -46,6 +46,8 @@ struct Sys {
     uint32_t c0, c1;    // bounding-box chunk range
     uint32_t n_crit;    // a cell splits while it holds >= n_crit particles
     uint32_t g;         // sink group size (<= 64)
+    uint32_t gcell;     // soft groups: chunking cells hold at most gcell * g particles
+    uint32_t pad;
     double invth2;      // 1 / theta^2 (+inf for theta = 0)
     double R2;          // hybrid cutoff, 0 in plain mode
 };

@@ -85,6 +85,7 @@ struct Request {
     const double *x;
     int64_t ldx;
     const float *m;
+    hipEvent_t ready = nullptr;    // recorded on the inputs' stream at submission
     St state = St::pending;
     htree_status status = HTREE_OK;
     Layout L{};
@@ -104,6 +105,7 @@ struct htree_server {
     std::vector<int32_t> load;            // requests running per stream
     int32_t per_stream = 1;
     std::vector<hipEvent_t> slot_ev;      // one completion event per slot
+    std::vector<hipEvent_t> ev_free;      // input-ready events not in use
     std::vector<int64_t> slot_req;        // request running in each slot, -1 if free
     CtxReport *report = nullptr;          // pinned, one per slot
     std::deque<int64_t> queue;            // pending, arrival order
@@ -121,7 +123,15 @@ double now_s(const htree_server *s) {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - s->t0).count();
 }
 
+// Returns a request's input-ready event to the pool (its wait, if any, was
+// enqueued before the request's own completion, so it has long been met).
+void drop_ready(htree_server *s, Request &r) {
+    if (r.ready) s->ev_free.push_back(r.ready);
+    r.ready = nullptr;
+}
+
 void finish(htree_server *s, int64_t id, Request &r, htree_status code) {
+    drop_ready(s, r);
     r.status = code;
     r.state = code == HTREE_OK ? St::done : St::failed;
     r.t_done = now_s(s);
@@ -144,6 +154,8 @@ htree_status enqueue_solve(htree_server *s, Request &r, char *blk, hipStream_t s
 htree_status launch(htree_server *s, Request &r) {
     char *blk = s->base + r.off;
     hipStream_t strm = s->streams[r.stream];
+    // the solve reads the inputs only after the work that wrote them
+    SRV_HIP(hipStreamWaitEvent(strm, r.ready, 0));
     htree_status e = htree_create(&r.ctx, &r.p, r.n, blk + r.L.ws, htree_workspace_bytes(&r.p, r.n),
                                   strm);
     if (e) return e;
@@ -275,7 +287,8 @@ htree_status htree_server_create(htree_server **out, void *d_arena, size_t arena
 }
 
 htree_status htree_server_submit(htree_server *s, const htree_params *p, int64_t n,
-                                 const double *d_x, int64_t ldx, const float *d_m, int64_t *id) {
+                                 const double *d_x, int64_t ldx, const float *d_m,
+                                 void *hip_input_stream, int64_t *id) {
     if (!s || !p || !id) return err(HTREE_EINVAL, "server, params or id is NULL");
     *id = 0;
     if (!d_x || !d_m) return err(HTREE_EINVAL, "x and m are required");
@@ -291,6 +304,14 @@ htree_status htree_server_submit(htree_server *s, const htree_params *p, int64_t
         return err(HTREE_ENOMEM, "footprint %zu bytes exceeds the arena (%zu)", L.total,
                    s->arena.size());
     Request r;
+    if (s->ev_free.empty()) {
+        hipEvent_t ev;
+        SRV_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        s->ev_free.push_back(ev);
+    }
+    r.ready = s->ev_free.back();
+    SRV_HIP(hipEventRecord(r.ready, (hipStream_t)hip_input_stream));
+    s->ev_free.pop_back();
     r.p = *p;
     r.n = n;
     r.x = d_x;
@@ -364,6 +385,7 @@ htree_status htree_server_release(htree_server *s, int64_t id) {
             }
         s->st.pending--;
         s->st.cancelled++;
+        drop_ready(s, r);
     } else {
         for (auto q = s->finished.begin(); q != s->finished.end(); ++q)
             if (*q == id) {
@@ -392,9 +414,12 @@ void htree_server_destroy(htree_server *s) {
     if (!s) return;
     for (size_t k = 0; k < s->slot_req.size(); k++)
         if (s->slot_req[k] >= 0) (void)hipEventSynchronize(s->slot_ev[k]);
-    for (auto &kv : s->req)
+    for (auto &kv : s->req) {
         if (kv.second.ctx) htree_destroy(kv.second.ctx);
+        if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
+    }
     for (hipEvent_t e : s->slot_ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : s->ev_free) (void)hipEventDestroy(e);
     if (s->report) (void)hipHostFree(s->report);
     delete s;
 }

@@ -63,7 +63,9 @@ class Server:
     # -- ABI --------------------------------------------------------------------
     def submit(self, params: Params, x, m) -> int:
         """Queues one solve.  ``x``: float64 device tensor [3, n] whose rows
-        may be strided (x[:, :n] of a larger array works); ``m``: float32 [n]."""
+        may be strided (x[:, :n] of a larger array works); ``m``: float32 [n].
+        The solve reads them after the work already enqueued on torch's
+        current stream (where they are normally written)."""
         torch = self.torch
         if x.dtype != torch.float64 or x.dim() != 2 or x.shape[0] != 3 or x.stride(1) != 1:
             raise ValueError("x must be a float64 [3, n] tensor with unit column stride")
@@ -73,9 +75,10 @@ class Server:
         if x.device != self.device or m.device != self.device:
             raise ValueError("inputs must live on the server's device")
         rid = C.c_int64()
+        producer = torch.cuda.current_stream(self.device).cuda_stream
         check(lib().htree_server_submit(self._h, C.byref(params), n, C.c_void_p(x.data_ptr()),
                                         int(x.stride(0)), C.c_void_p(m.data_ptr()),
-                                        C.byref(rid)))
+                                        C.c_void_p(producer), C.byref(rid)))
         self._inputs[rid.value] = (x, m)
         return rid.value
 

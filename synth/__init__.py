@@ -25,7 +25,7 @@ from dataclasses import dataclass
 import numpy as np
 
 __all__ = [
-    "plummer", "hernquist", "cold_cube", "sample_indices",
+    "plummer", "hernquist", "cold_cube", "lognormal_masses", "sample_indices",
     "r2_for_neighbours", "Workload", "WORKLOADS", "ensemble_sizes",
     "serving_requests",
 ]
@@ -99,6 +99,13 @@ def cold_cube(n: int, seed: int, half: float = 1.0, M: float = 1.0):
     v = np.zeros((3, n))
     m = np.full(n, M / n)
     return np.ascontiguousarray(x), v, m
+
+
+def lognormal_masses(n: int, seed: int, sigma: float = 1.0, M: float = 1.0) -> np.ndarray:
+    """``n`` masses exp(N(0, sigma^2)) scaled to total M (float64)."""
+    rng = _rng(seed)
+    m = np.exp(rng.normal(0.0, sigma, n))
+    return m * (M / m.sum())
 
 
 def sample_indices(n: int, k: int, seed: int) -> np.ndarray:

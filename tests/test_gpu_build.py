@@ -26,10 +26,17 @@ def _case(name):
         return x, v, m
     if name == "hernquist20k":
         return synth.hernquist(20000, 46)
+    if name == "lognormal4k":
+        x, v, _ = synth.plummer(4096, 1)
+        return x, v, synth.lognormal_masses(4096, 49)
+    if name == "dups_lognormal":
+        x, v, _ = _case("dups")
+        return x, v, synth.lognormal_masses(5000, 50)
     raise KeyError(name)
 
 
-CASES = ["plummer4k", "ragged1000", "cube3001", "tiny1", "small15", "dups", "hernquist20k"]
+CASES = ["plummer4k", "ragged1000", "cube3001", "tiny1", "small15", "dups", "hernquist20k",
+         "lognormal4k", "dups_lognormal"]
 
 
 @pytest.mark.parametrize("case", CASES)

@@ -19,19 +19,21 @@ def _requests(count, seed, lo=10.0, hi=15.0):
         n = int(np.rint(2.0 ** rng.uniform(lo, hi)))
         model = "plummer" if rng.random() < 0.5 else "cube"
         x, _, m = (synth.plummer if model == "plummer" else synth.cold_cube)(n, seed * 1000 + k)
+        if k % 2:
+            m = synth.lognormal_masses(n, seed * 1000 + k + 500)
         R2 = synth.r2_for_neighbours(model, n, 64)
         pad = int(rng.integers(0, 300))
         xb = np.zeros((3, n + pad))
         xb[:, :n] = x
         out.append(dict(n=n, x=x, xb=xb, m=m.astype(np.float32), hybrid=int(k % 5 != 4),
                         theta=float(rng.uniform(0.4, 0.7)), eps=0.01 * (2.0 ** 20 / n) ** (1 / 3),
-                        R2=R2, pot=(k % 3 == 0)))
+                        R2=R2, pot=(k % 3 == 0), G=(1.0, 2.5, 2.0 ** 20 / n)[k % 3]))
     return out
 
 
 def _params(P, r):
-    return P.default_params(eps=r["eps"], theta=r["theta"], R1=r["R2"] / 2, R2=r["R2"],
-                            hybrid=r["hybrid"], flags=P.F_POT if r["pot"] else 0)
+    return P.default_params(G=r["G"], eps=r["eps"], theta=r["theta"], R1=r["R2"] / 2,
+                            R2=r["R2"], hybrid=r["hybrid"], flags=P.F_POT if r["pot"] else 0)
 
 
 def _collect(P, torch, srv, reqs, ids, keep, limit_s=60.0):
@@ -93,17 +95,45 @@ def test_serve_alone_equals_mix(orc):
         inf, a_s, a_h, ngb, pot = mix[rid]
         m64 = r["m"].astype(np.float64)
         T = orc.Tree(r["x"], m64, n_crit=16, theta=r["theta"])
-        oa, _, oi = T.soft(1.0, r["eps"], r["R2"] / 2, r["R2"], r["hybrid"])
+        oa, _, oi = T.soft(r["G"], r["eps"], r["R2"] / 2, r["R2"], r["hybrid"])
         e = rel_err(a_s.cpu().numpy().astype(np.float64), oa)
         assert np.percentile(e, 99) <= 1e-5, k
         assert inf["soft_interactions"] == oi, k
         if r["hybrid"]:
-            oh, _, ongb = orc.split_direct(r["x"], m64, 1.0, r["eps"], r["R2"] / 2, r["R2"],
+            oh, _, ongb = orc.split_direct(r["x"], m64, r["G"], r["eps"], r["R2"] / 2, r["R2"],
                                            soft=False)
             assert np.array_equal(ngb.cpu().numpy(), ongb), k
+            eh = rel_err(a_h.cpu().numpy().astype(np.float64), oh)[ongb > 0]
+            assert np.percentile(eh, 99) <= 1e-5, k
             assert inf["hard_pairs"] == int(ongb.sum()), k
         else:
             assert a_h is None and ngb is None
+
+
+def test_serve_waits_for_inputs_written_on_a_side_stream():
+    """Inputs written by GPU work on the caller's (side) stream just before
+    submission: the solve must read them only after that work."""
+    torch, P = need_gpu()
+    r = _requests(1, 7, 14.0, 14.0)[0]
+    x_host, m_host = _inputs(torch, r)
+    with P.Server(P.solve_footprint(_params(P, r), r["n"]) + (1 << 20), 1, 1) as srv:
+        rid = srv.submit(_params(P, r), x_host, m_host)
+        ref = _collect(P, torch, srv, [r], [rid], False)[rid]
+        side = torch.cuda.Stream()
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            x = torch.zeros_like(x_host)
+            m = torch.zeros_like(m_host)
+            torch.cuda._sleep(50_000_000)       # keeps the side stream busy
+            x.copy_(x_host)
+            m.copy_(m_host)
+            rid = srv.submit(_params(P, r), x, m)
+        got = _collect(P, torch, srv, [r], [rid], False)[rid]
+    assert got[0]["status"] == 0
+    for u, v in zip(ref[1:], got[1:]):
+        assert (u is None) == (v is None)
+        if u is not None:
+            assert torch.equal(u, v)
 
 
 def test_serve_admission_and_errors():

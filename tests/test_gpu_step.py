@@ -16,15 +16,20 @@ def _run_gpu(P, torch, x, v32, m32, steps, **kw):
     return xg.cpu().numpy(), vg.cpu().numpy().astype(np.float64)
 
 
-@pytest.mark.parametrize("n_sub,dt,steps", [(1, 1.0 / 128, 10), (2, 2.0 / 128, 5), (4, 4.0 / 128, 3)])
-def test_step_matches_oracle(orc, n_sub, dt, steps):
+@pytest.mark.parametrize("n_sub,dt,steps,precision", [(1, 1.0 / 128, 10, 0), (2, 2.0 / 128, 5, 0),
+                                                     (4, 4.0 / 128, 3, 0), (1, 1.0 / 128, 10, 1),
+                                                     (2, 2.0 / 128, 5, 1)])
+def test_step_matches_oracle(orc, n_sub, dt, steps, precision):
+    """The small Plummer run (N = 4096, eps = 1/64, ten steps of 1/128 and its
+    two-timestep variants), with FP32 and FP64 (precision 1) soft
+    interactions, against the oracle's nested kick-drift-kick."""
     torch, P = need_gpu()
     wl = synth.WORKLOADS["plummer4k"]
     x, v, m = wl.make()
     x, v32, m32, v64, m64 = as_inputs(x, v, m)
-    print("step n_sub", n_sub, "dt", dt, "steps", steps, flush=True)
+    print("step n_sub", n_sub, "dt", dt, "steps", steps, "precision", precision, flush=True)
     xg, vg = _run_gpu(P, torch, x, v32, m32, steps, eps=wl.eps, theta=wl.theta, R1=wl.R1,
-                      R2=wl.R2, dt_soft=dt, n_sub=n_sub)
+                      R2=wl.R2, dt_soft=dt, n_sub=n_sub, precision=precision)
     xo, vo = orc.step(x, v64, m64, 1.0, wl.eps, wl.theta, wl.R1, wl.R2, 16, 64, 1, dt, n_sub,
                       steps)
     dx = np.abs(xg - xo).max()

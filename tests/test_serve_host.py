@@ -69,7 +69,8 @@ def test_server_argument_errors(abi):
     # calls on a NULL server
     rid = C.c_int64()
     p = abi.default_params()
-    assert L.htree_server_submit(None, C.byref(p), 10, None, 10, None, C.byref(rid)) == abi.HTREE_EINVAL
+    assert L.htree_server_submit(None, C.byref(p), 10, None, 10, None, None,
+                                 C.byref(rid)) == abi.HTREE_EINVAL
     nd = C.c_int32()
     assert L.htree_server_poll(None, None, 0, C.byref(nd)) == abi.HTREE_EINVAL
     assert L.htree_server_release(None, 1) == abi.HTREE_EINVAL
