@@ -118,6 +118,25 @@ int32_t htree_system_count(htree_ctx *ctx);
 htree_status htree_create(htree_ctx **ctx, const htree_params *p, int64_t n,
                           void *d_workspace, size_t ws_bytes, void *hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): as
+ * htree_create for one system of n particles, but the workspace is the
+ * library's own static device array of 64 MiB (HTREE_STATIC_SCRATCH_BYTES),
+ * one per device, held from its first use until the process ends.  No device
+ * memory is allocated by this call or by any later call on the context; the
+ * caller still passes every input and output buffer.  The limit: n must need
+ * at most that many workspace bytes (htree_workspace_bytes; about 750 bytes
+ * per particle with n_crit = 16, so n <= 2^16 fits), else ENOMEM.  One context
+ * per device may hold the array at a time: ESTATE while another is alive.
+ * htree_destroy of such a context first waits for its stream, so the next
+ * one does not overwrite work still running.  The array keeps the last
+ * context's contents; everything a context needs zeroed is cleared on the
+ * device at creation.  Contexts on different devices are independent.
+ * Errors: EINVAL, ENOMEM, ESTATE, EDEVICE. */
+#define HTREE_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+htree_status htree_create_static(htree_ctx **ctx, const htree_params *p, int64_t n,
+                                 void *hip_stream);
+
 /* Copies the particle state in.  d_x [3][n] float64, d_v [3][n] float32 (may be
  * NULL: zero velocities), d_m [n] float32.  Invalidates the tree and forces. */
 htree_status htree_set_state(htree_ctx *ctx, const double *d_x, const float *d_v,

@@ -11,13 +11,13 @@ from __future__ import annotations
 
 import ctypes as C
 
-from ._abi import (F_POT, F_TIMING, HTREE_EINVAL, HTREE_ENOMEM, HTREE_EOVERFLOW, HTREE_ESTATE,
+from ._abi import (F_POT, F_TIMING, STATIC_SCRATCH_BYTES, HTREE_EINVAL, HTREE_ENOMEM, HTREE_EOVERFLOW, HTREE_ESTATE,
                    HTreeError, Params, Counters, batch_arrays, batch_workspace_bytes, check,
                    default_params, lib, solve_footprint, workspace_bytes)
 from .server import Server
 
 __all__ = ["HTree", "Server", "solve_footprint", "Params", "Counters", "HTreeError", "default_params", "workspace_bytes",
-           "batch_workspace_bytes", "lib", "F_POT", "F_TIMING", "HTREE_EINVAL", "HTREE_ENOMEM",
+           "batch_workspace_bytes", "lib", "F_POT", "F_TIMING", "STATIC_SCRATCH_BYTES", "HTREE_EINVAL", "HTREE_ENOMEM",
            "HTREE_EOVERFLOW", "HTREE_ESTATE"]
 
 
@@ -33,9 +33,11 @@ class HTree:
     ``n`` the list of their sizes (arrays then concatenate the systems in
     order).  The workspace is a torch uint8 tensor on ``device``; calls are
     enqueued on ``stream`` (default: torch's current stream at construction).
+    ``static=True`` (one system only) uses the library's static device scratch
+    instead (htree_create_static): nothing is allocated for the workspace.
     """
 
-    def __init__(self, n, params, device="cuda", stream=None):
+    def __init__(self, n, params, device="cuda", stream=None, static=False):
         import torch
         self.torch = torch
         self.batch = isinstance(n, (list, tuple))
@@ -45,6 +47,16 @@ class HTree:
         self.device = torch.device(device)
         with torch.cuda.device(self.device):
             self.stream = stream if stream is not None else torch.cuda.current_stream()
+            if static:
+                if self.batch:
+                    raise ValueError("the static scratch serves one system")
+                h = C.c_void_p()
+                self.nbytes = 0
+                self.workspace = None
+                check(lib().htree_create_static(C.byref(h), C.byref(params), self.n,
+                                                C.c_void_p(self.stream.cuda_stream)))
+                self._h = h
+                return
             if self.batch:
                 pa, na = batch_arrays(params, self.sizes)
                 nbytes = int(lib().htree_batch_workspace_bytes(pa, na, len(self.sizes)))

@@ -20,6 +20,7 @@ HTREE_EOVERFLOW = -4
 HTREE_ESTATE = -5
 F_POT = 1
 F_TIMING = 2
+STATIC_SCRATCH_BYTES = 64 << 20   # HTREE_STATIC_SCRATCH_BYTES
 
 _NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFLOW", -5: "ESTATE"}
 
@@ -92,6 +93,7 @@ def lib() -> C.CDLL:
     L.htree_workspace_bytes.argtypes = [C.POINTER(Params), C.c_int64]
     L.htree_workspace_bytes.restype = C.c_size_t
     L.htree_create.argtypes = [C.POINTER(_p), C.POINTER(Params), C.c_int64, _p, C.c_size_t, _p]
+    L.htree_create_static.argtypes = [C.POINTER(_p), C.POINTER(Params), C.c_int64, _p]
     L.htree_batch_workspace_bytes.argtypes = [_p, _p, C.c_int32]
     L.htree_batch_workspace_bytes.restype = C.c_size_t
     L.htree_batch_create.argtypes = [C.POINTER(_p), _p, _p, C.c_int32, _p, C.c_size_t, _p]
@@ -133,7 +135,7 @@ def lib() -> C.CDLL:
     for name in ("htree_server_create", "htree_server_submit", "htree_server_poll",
                  "htree_server_result", "htree_server_release", "htree_server_get_stats"):
         getattr(L, name).restype = _st
-    for name in ("htree_create", "htree_batch_create", "htree_set_state", "htree_build_tree", "htree_soft_force",
+    for name in ("htree_create", "htree_create_static", "htree_batch_create", "htree_set_state", "htree_build_tree", "htree_soft_force",
                  "htree_hard_force", "htree_kick_drift", "htree_step", "htree_get_state",
                  "htree_sync", "htree_stats", "htree_group_counts", "htree_export_keys",
                  "htree_export_nodes", "htree_export_groups"):

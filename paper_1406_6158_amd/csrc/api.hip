@@ -11,6 +11,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -137,6 +138,7 @@ struct htree_ctx {
     bool hard_order = false;           // B.horder holds an order for the current hard groups
     bool forces_current = false;
     bool timing = false;
+    bool on_scratch = false;           // carved from the library's static scratch
     std::vector<hipEvent_t> ev[3];     // per phase: start/end pairs since the last stats
     int ev_n[3] = {0, 0, 0};
     int calls[3] = {0, 0, 0};
@@ -460,6 +462,26 @@ htree_status ensure_forces(htree_ctx *c) {
 
 }  // namespace
 
+// ---------------------------------------------------------------------------
+// Static scratch: the workspace of htree_create_static, for callers that
+// cannot allocate device memory.  Each device holds its own copy until the
+// process ends; one context at a time may use it.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = HTREE_STATIC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];      // device address of scratch, per device
+bool g_scratch_held[kMaxDevices];      // a live context uses it
+
+htree_status create_ctx(htree_ctx **out, const htree_params *p, const int64_t *n, int32_t S,
+                        void *ws, size_t ws_bytes, void *stream);
+
+}  // namespace
+
 extern "C" {
 
 void htree_default_params(htree_params *p) {
@@ -490,6 +512,63 @@ size_t htree_workspace_bytes(const htree_params *p, int64_t n) {
 
 htree_status htree_batch_create(htree_ctx **out, const htree_params *p, const int64_t *n,
                                 int32_t S, void *ws, size_t ws_bytes, void *stream) {
+    return create_ctx(out, p, n, S, ws, ws_bytes, stream);
+}
+
+htree_status htree_create(htree_ctx **out, const htree_params *p, int64_t n, void *ws,
+                          size_t ws_bytes, void *stream) {
+    return htree_batch_create(out, p, &n, 1, ws, ws_bytes, stream);
+}
+
+htree_status htree_create_static(htree_ctx **out, const htree_params *p, int64_t n,
+                                 void *stream) {
+    if (!out) return fail(HTREE_EINVAL, "out is NULL");
+    *out = nullptr;
+    htree_status st = validate(p, &n, 1);
+    if (st) return st;
+    const size_t need = footprint(p, &n, 1);
+    if (need > kScratchBytes)
+        return fail(HTREE_ENOMEM,
+                    "n = %lld needs %zu workspace bytes, more than the %zu of the static scratch",
+                    (long long)n, need, kScratchBytes);
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(HTREE_EINVAL, "device %d out of range", dev);
+    void *ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch_ptr[dev]) {
+            // the array's name is a host-side stand-in; its device address is
+            // looked up once per device, with that device current
+            void *ptr = nullptr;
+            hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr)
+                return fail(HTREE_EDEVICE, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                            hipGetErrorString(e));
+            g_scratch_ptr[dev] = ptr;
+        }
+        if (g_scratch_held[dev])
+            return fail(HTREE_ESTATE, "the static scratch of device %d is held by another "
+                        "context; destroy that one first", dev);
+        g_scratch_held[dev] = true;
+        ws = g_scratch_ptr[dev];
+    }
+    st = create_ctx(out, p, &n, 1, ws, kScratchBytes, stream);
+    if (st) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        g_scratch_held[dev] = false;
+        return st;
+    }
+    (*out)->on_scratch = true;
+    return HTREE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+htree_status create_ctx(htree_ctx **out, const htree_params *p, const int64_t *n, int32_t S,
+                        void *ws, size_t ws_bytes, void *stream) {
     if (!out) return fail(HTREE_EINVAL, "out is NULL");
     *out = nullptr;
     htree_status st = validate(p, n, S);
@@ -543,10 +622,9 @@ htree_status htree_batch_create(htree_ctx **out, const htree_params *p, const in
     return HTREE_OK;
 }
 
-htree_status htree_create(htree_ctx **out, const htree_params *p, int64_t n, void *ws,
-                          size_t ws_bytes, void *stream) {
-    return htree_batch_create(out, p, &n, 1, ws, ws_bytes, stream);
-}
+}  // namespace
+
+extern "C" {
 
 int32_t htree_system_count(htree_ctx *c) { return c ? c->S : -1; }
 
@@ -796,6 +874,13 @@ void htree_destroy(htree_ctx *c) {
     (void)hipSetDevice(c->device);
     for (int k = 0; k < 3; k++)
         for (hipEvent_t e : c->ev[k]) (void)hipEventDestroy(e);
+    if (c->on_scratch) {
+        // the next context on this device's scratch must not overwrite it
+        // while this one's work is still running
+        (void)hipStreamSynchronize(c->stream);
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        g_scratch_held[c->device] = false;
+    }
     delete c;
 }
 

@@ -43,6 +43,8 @@
 #define __shared__ static
 #define __launch_bounds__(...)
 #define __forceinline__ inline
+#define __align__(n) alignas(n)
+#define HIP_SYMBOL(x) (&(x))
 
 struct dim3 {
     unsigned x, y, z;
@@ -417,6 +419,11 @@ inline hipError_t hipEventElapsedTime(float *ms, hipEvent_t a, hipEvent_t b) {
 inline hipError_t hipHostMalloc(void **p, size_t n, unsigned = 0) {
     *p = calloc(1, n ? n : 1);
     return *p ? hipSuccess : hipErrorInvalidValue;
+}
+// device symbols are ordinary host objects in the emulation
+inline hipError_t hipGetSymbolAddress(void **p, const void *sym) {
+    *p = const_cast<void *>(sym);
+    return hipSuccess;
 }
 inline hipError_t hipHostFree(void *p) {
     free(p);

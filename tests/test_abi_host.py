@@ -116,3 +116,19 @@ def test_batch_workspace_and_validation(abi):
 def test_precision_fp64_accepted(abi):
     p = abi.default_params(precision=1)
     assert abi.workspace_bytes(p, 1000) > 0
+
+
+def test_create_static_rejects_before_any_device_call(abi):
+    """The static-scratch context refuses sizes whose workspace exceeds the
+    scratch (ENOMEM) and bad arguments (EINVAL) before touching a device."""
+    p = abi.default_params()
+    L = abi.lib()
+    h = C.c_void_p()
+    assert abi.workspace_bytes(p, 1 << 16) <= abi.STATIC_SCRATCH_BYTES
+    big = 1 << 17
+    assert abi.workspace_bytes(p, big) > abi.STATIC_SCRATCH_BYTES
+    assert L.htree_create_static(C.byref(h), C.byref(p), big, None) == abi.HTREE_ENOMEM
+    assert b"static scratch" in L.htree_last_error()
+    assert L.htree_create_static(None, C.byref(p), 1000, None) == abi.HTREE_EINVAL
+    assert L.htree_create_static(C.byref(h), C.byref(p), 0, None) == abi.HTREE_EINVAL
+    assert not h.value
