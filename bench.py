@@ -278,7 +278,7 @@ def ensemble(P, torch, steps, count=512):
                             v=torch.from_numpy(v.astype(np.float32)).cuda(),
                             m=torch.from_numpy(m.astype(np.float32)).cuda()))
 
-    def mk(k, g, nc, flags=P.F_TIMING):
+    def mk(k, g, nc, flags=P.F_TIMING | P.F_REUSE):
         n = sizes[k]
         R2 = synth.r2_for_neighbours("plummer", n, 32)
         return P.default_params(eps=4.0 / n ** (1.0 / 3.0), theta=0.5, R1=R2 / 2, R2=R2,
@@ -286,7 +286,7 @@ def ensemble(P, torch, steps, count=512):
                                 group_size=g, flags=flags)
 
     table, times = autotune.tune(P, torch, systems, mk, log=_log)
-    params = [mk(k, *table[autotune.size_class(n)], flags=0) for k, n in enumerate(sizes)]
+    params = [mk(k, *table[autotune.size_class(n)], flags=P.F_REUSE) for k, n in enumerate(sizes)]
     x = torch.cat([s["x"] for s in systems], dim=1)
     v = torch.cat([s["v"] for s in systems], dim=1)
     m = torch.cat([s["m"] for s in systems])
@@ -466,9 +466,12 @@ def main():
     x, v, m = wl.make()
     v32 = v.astype(np.float32)
     m32 = m.astype(np.float32)
+    # the hard searches recorded after each build are replayed on the three
+    # refitted substeps (exact neighbour sets; measured faster than walking
+    # from the root every substep)
     params = P.default_params(eps=wl.eps, theta=wl.theta, R1=wl.R1, R2=wl.R2,
                               dt_soft=wl.dt_soft, n_sub=wl.n_sub, hybrid=1, n_crit=wl.n_crit,
-                              flags=P.F_TIMING)
+                              flags=P.F_TIMING | P.F_REUSE)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t = P.HTree(wl.n, params, device=dev)
@@ -530,7 +533,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "plummer N=2^20 eps=0.01 theta=0.5 ngb~64 n_sub=4 dt_h=1/64",
                    "n": wl.n, "theta": wl.theta, "eps": wl.eps, "R2": wl.R2, "n_sub": wl.n_sub,
-                   "group": 64, "n_crit": wl.n_crit},
+                   "group": 64, "n_crit": wl.n_crit, "hard_search_reuse": True},
         "soft_interactions_per_step": soft_inter,
         "hard_pairs_per_step": hard_pairs,
         "hard_candidates_per_step": st["hard_candidates"] / K,

@@ -52,6 +52,8 @@ typedef int32_t htree_status;
 /* htree_params.flags */
 #define HTREE_F_POT     1     /* soft_force also evaluates the tree potential     */
 #define HTREE_F_TIMING  2     /* record per-phase times with HIP events           */
+#define HTREE_F_REUSE   4     /* hard force: reuse the search between builds      */
+                              /* (htree_hard_force describes it)                  */
 
 typedef struct {
     double  G;            /* gravitational constant (> 0)                            */
@@ -157,6 +159,11 @@ htree_status htree_soft_force(htree_ctx *ctx, float *d_acc, float *d_pot);
 
 /* Hard force, section II.C: for every sink the exact neighbour set
  * { j != i : |x_j - x_i|^2 < R2^2 } (FP64 test) and the sum of K(r) F_ij.
+ * With HTREE_F_REUSE, the first launch after a build records each group's
+ * search (the tree nodes it tests and does not open, with the opening radius
+ * widened by R2/4) and the launches after htree_refit replay it against the
+ * refitted boxes instead of walking from the root; the neighbour sets stay
+ * exact, the pair terms are summed in another order.
  * Kept for the integrator; written in caller order if d_acc / d_ngb (int32
  * neighbour counts) are not NULL.  ESTATE without a current tree; EINVAL in
  * plain mode. */
@@ -178,6 +185,16 @@ htree_status htree_kick_drift(htree_ctx *ctx, double dt_kick, const float *d_acc
  * exact either way.  Plain mode: n_sub = 1 with the full tree force.  Forces
  * at the initial positions are computed on the first call. */
 htree_status htree_step(htree_ctx *ctx, int32_t n_soft_steps);
+
+/* Recomputes the node boxes of the last build at the current positions:
+ * the same tree, particle order and groups, with boxes that bound the drifted
+ * particles.  This is what the hard substeps of section II.C need (the hard
+ * force is evaluated after every drift of dt_h, the tree is rebuilt only for
+ * the soft force): after htree_kick_drift, htree_refit makes
+ * htree_hard_force valid again (its neighbour sets stay exact); the soft
+ * force still needs htree_build_tree.  ESTATE if no tree was built since
+ * htree_set_state. */
+htree_status htree_refit(htree_ctx *ctx);
 
 /* Copies positions / velocities out in caller order (either may be NULL). */
 htree_status htree_get_state(htree_ctx *ctx, double *d_x, float *d_v);

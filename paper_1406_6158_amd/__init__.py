@@ -11,13 +11,13 @@ from __future__ import annotations
 
 import ctypes as C
 
-from ._abi import (F_POT, F_TIMING, STATIC_SCRATCH_BYTES, HTREE_EINVAL, HTREE_ENOMEM, HTREE_EOVERFLOW, HTREE_ESTATE,
+from ._abi import (F_POT, F_TIMING, F_REUSE, STATIC_SCRATCH_BYTES, HTREE_EINVAL, HTREE_ENOMEM, HTREE_EOVERFLOW, HTREE_ESTATE,
                    HTreeError, Params, Counters, batch_arrays, batch_workspace_bytes, check,
                    default_params, lib, solve_footprint, workspace_bytes)
 from .server import Server
 
 __all__ = ["HTree", "Server", "solve_footprint", "Params", "Counters", "HTreeError", "default_params", "workspace_bytes",
-           "batch_workspace_bytes", "lib", "F_POT", "F_TIMING", "STATIC_SCRATCH_BYTES", "HTREE_EINVAL", "HTREE_ENOMEM",
+           "batch_workspace_bytes", "lib", "F_POT", "F_TIMING", "F_REUSE", "STATIC_SCRATCH_BYTES", "HTREE_EINVAL", "HTREE_ENOMEM",
            "HTREE_EOVERFLOW", "HTREE_ESTATE"]
 
 
@@ -152,6 +152,10 @@ class HTree:
         a = None if acc is None else self._dev(acc, self.torch.float32, (3, self.n))
         check(lib().htree_kick_drift(self._h, float(dt_kick), _ptr(a), float(dt_drift)))
         self._keep = a
+        return self
+
+    def refit(self):
+        check(lib().htree_refit(self._h))
         return self
 
     def step(self, n_soft_steps=1):

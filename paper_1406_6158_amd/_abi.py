@@ -20,6 +20,7 @@ HTREE_EOVERFLOW = -4
 HTREE_ESTATE = -5
 F_POT = 1
 F_TIMING = 2
+F_REUSE = 4
 STATIC_SCRATCH_BYTES = 64 << 20   # HTREE_STATIC_SCRATCH_BYTES
 
 _NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "EOVERFLOW", -5: "ESTATE"}
@@ -105,6 +106,7 @@ def lib() -> C.CDLL:
     L.htree_hard_force.argtypes = [_p, _p, _p]
     L.htree_kick_drift.argtypes = [_p, C.c_double, _p, C.c_double]
     L.htree_step.argtypes = [_p, C.c_int32]
+    L.htree_refit.argtypes = [_p]
     L.htree_get_state.argtypes = [_p, _p, _p]
     L.htree_sync.argtypes = [_p]
     L.htree_stats.argtypes = [_p, C.POINTER(Counters)]
@@ -136,7 +138,7 @@ def lib() -> C.CDLL:
                  "htree_server_result", "htree_server_release", "htree_server_get_stats"):
         getattr(L, name).restype = _st
     for name in ("htree_create", "htree_create_static", "htree_batch_create", "htree_set_state", "htree_build_tree", "htree_soft_force",
-                 "htree_hard_force", "htree_kick_drift", "htree_step", "htree_get_state",
+                 "htree_hard_force", "htree_kick_drift", "htree_step", "htree_refit", "htree_get_state",
                  "htree_sync", "htree_stats", "htree_group_counts", "htree_export_keys",
                  "htree_export_nodes", "htree_export_groups"):
         getattr(L, name).restype = _st

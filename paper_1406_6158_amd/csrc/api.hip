@@ -70,7 +70,8 @@ htree_status validate_one(const htree_params *p, int64_t n) {
         return fail(HTREE_EINVAL, "group_size must be in [1, 64]");
     if (p->precision != 0 && p->precision != 1)
         return fail(HTREE_EINVAL, "precision must be 0 (FP32) or 1 (FP64 interactions)");
-    if (p->flags & ~(HTREE_F_POT | HTREE_F_TIMING)) return fail(HTREE_EINVAL, "unknown flags");
+    if (p->flags & ~(HTREE_F_POT | HTREE_F_TIMING | HTREE_F_REUSE))
+        return fail(HTREE_EINVAL, "unknown flags");
     if (p->group_cell < 1 || p->group_cell > 4096)
         return fail(HTREE_EINVAL, "group_cell must be in [1, 4096]");
     return HTREE_OK;
@@ -136,6 +137,8 @@ struct htree_ctx {
     bool tree = false, moments = false, have_soft = false, have_hard = false;
     bool boxes = false;                // node boxes fit the current positions (hard walk)
     bool hard_order = false;           // B.horder holds an order for the current hard groups
+    bool hard_lists = false;           // B.hlist holds recorded searches over the current tree
+    bool topo = false;                 // a tree was built since the last set_state
     bool forces_current = false;
     bool timing = false;
     bool on_scratch = false;           // carved from the library's static scratch
@@ -235,6 +238,8 @@ void carve(Carver &C, htree_ctx *c) {
     B.hkey = C.take<uint32_t>(2 * n);
     B.hval = C.take<uint32_t>(2 * n);
     B.horder = C.take<uint32_t>(n);
+    B.hlist = C.take<uint32_t>((int64_t)kListPerSink * n);
+    B.hlen = C.take<uint32_t>(n);
     B.ndisp = C.take<uint32_t>(4);
     c->tmp3 = C.take<float>(3 * n);
     c->pot = C.take<float>(n);
@@ -333,6 +338,9 @@ ForceArgs force_args(htree_ctx *c) {
     A.order = nullptr;
     A.cost = nullptr;
     A.wsoft = nullptr;
+    A.hlist = nullptr;
+    A.hlen = nullptr;
+    A.hmode = 0;
     A.n = c->n;
     A.acc = nullptr;
     A.pot = nullptr;
@@ -378,6 +386,8 @@ htree_status do_build(htree_ctx *c, bool moments, bool keep_acc = true) {
     c->tree = true;
     c->boxes = true;
     c->hard_order = false;
+    c->hard_lists = false;
+    c->topo = true;
     c->moments = moments;
     return HTREE_OK;
 }
@@ -424,11 +434,19 @@ htree_status do_hard(htree_ctx *c) {
     // costs, which order the later launches (after refits)
     A.order = c->B.horder;
     A.cost = c->hard_order ? nullptr : c->B.hcost;
+    // with reuse, the first launch over a tree records each group's search
+    // (widened by the skin); the launches after refits replay it against the
+    // new boxes
+    const bool reuse = (c->p.flags & HTREE_F_REUSE) != 0;
+    A.hlist = c->B.hlist;
+    A.hlen = c->B.hlen;
+    A.hmode = !reuse ? 0 : c->hard_lists ? 2 : 1;
     ev_begin(c, 2);
     launch_hard(A, c->n_wg, c->stream);
     if (!c->hard_order) launch_hard_order(c->B, c->stream);
     ev_end(c, 2);
     c->hard_order = true;
+    c->hard_lists = true;
     HIP_OK(hipGetLastError());
     c->have_hard = true;
     return HTREE_OK;
@@ -684,6 +702,12 @@ htree_status htree_kick_drift(htree_ctx *c, double dt_kick, const float *d_acc, 
     return HTREE_OK;
 }
 
+htree_status htree_refit(htree_ctx *c) {
+    CTX_CHECK(c);
+    if (!c->topo) return fail(HTREE_ESTATE, "refit needs a built tree");
+    return do_refit(c);
+}
+
 htree_status htree_step(htree_ctx *c, int32_t n_soft) {
     CTX_CHECK(c);
     if (n_soft < 0) return fail(HTREE_EINVAL, "n_soft_steps must be >= 0");
@@ -900,6 +924,7 @@ htree_status htree::ctx_set_state(htree_ctx *c, const double *d_x, int64_t ldx, 
     HIP_OK(hipGetLastError());
     c->tree = c->moments = c->boxes = c->have_soft = c->have_hard = c->forces_current = false;
     c->hard_order = false;
+    c->topo = false;
     return HTREE_OK;
 }
 

@@ -225,6 +225,8 @@ __global__ __launch_bounds__(kBoxNT) void k_frame(const double *part, const Sys 
     // slack covers the rounding of build-frame differences against FP64 x
     double R2p = S.R2 + ldexp(side, -40);
     F.R2pad2 = R2p * R2p;
+    double R2r = S.R2 * (1.0 + kHardSkin) + ldexp(side, -40);
+    F.R2rec2 = R2r * R2r;
 }
 
 __device__ inline uint64_t spread3(uint32_t v) {

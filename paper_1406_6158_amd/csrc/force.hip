@@ -643,6 +643,7 @@ __device__ inline double rsqrt64(double s) {
     return y * fma(-0.5 * s, y * y, 1.5);
 }
 
+template <int MODE>
 __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
     const int lane = __lane_id();
     const uint64_t lt = lanemask_lt();
@@ -675,9 +676,33 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
     // removed from the neighbour count at the end.
     double hx = 0.0, hy = 0.0, hz = 0.0;
     uint32_t ngb = 0, cand = 0, trips = 0;
-    int top = 1, nl = 0, nr = 0, nst = 0;
-    uint32_t avail = 1, tot = 0;
-    if (lane == 0) {
+
+    // Search reuse between builds.  Record (mode 1): the walk opens the nodes
+    // within the widened radius R2rec and keeps, in the group's list, every
+    // node it tests and does not open; the leaves among them within R2 are
+    // collected now.  Those nodes' subtrees cover every leaf exactly once.
+    // Replay (mode 2, later launches over the same tree, boxes refitted to
+    // new positions): the walk starts from the kept nodes instead of the
+    // root and tests them against the current boxes with R2 -- close leaves
+    // are collected, close inner nodes opened -- so the collected leaves are
+    // exactly those a walk from the root would collect.
+    constexpr int mode = MODE;   // 0 walk from the root, 1 record, 2 replay
+    const int64_t lbase = (int64_t)kListPerSink * b0;
+    const uint32_t lcap = kListPerSink * (uint32_t)ns;
+    uint32_t elen = 0, epos = 0, hl = 0;
+    bool from_root = true;
+    if constexpr (mode == 2) {
+        const uint32_t L = A.hlen[grp];
+        if (L != kNoList) {
+            elen = L;
+            from_root = false;
+        }
+    }
+    constexpr bool record = mode == 1;
+    const double padw2 = record ? A.frame[sys].R2rec2 : pad2;   // opening radius
+    int top = from_root ? 1 : 0, nl = 0, nr = 0, nst = 0;
+    uint32_t avail = from_root ? 1u : 0u, tot = 0;
+    if (lane == 0 && from_root) {
         S.efirst[0] = sys;
         S.ecnt[0] = 1;
     }
@@ -773,20 +798,30 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
     };
 
     // The walk collects leaves into the batch until the shared entries run
-    // short, then the batch is gathered.
-    while (avail > 0) {
+    // short, then the batch is gathered.  Nodes come from the stack of pushed
+    // child ranges first, then from the replayed list.
+    while (avail > 0 || epos < elen) {
         // one entry beyond the depth-first reserve is kept for a leaf
         int room = kHardEnt - kStkReserve - 1 - top - nl;
         if (nl > 0 && room < 64) {
             drain_batch();
             room = kHardEnt - kStkReserve - 1 - top;
         }
-        int want = avail < 64u ? (int)avail : 64;
-        if (want > room) want = room > 1 ? room : 1;
-        uint32_t id = take_items(S.efirst, S.ecnt, top, want, S.scan);
-        avail -= (uint32_t)want;
+        uint32_t id = 0;
+        int want;
+        if (mode != 2 || avail > 0) {
+            want = avail < 64u ? (int)avail : 64;
+            if (want > room) want = room > 1 ? room : 1;
+            id = take_items(S.efirst, S.ecnt, top, want, S.scan);
+            avail -= (uint32_t)want;
+        } else {
+            want = elen - epos < 64u ? (int)(elen - epos) : 64;
+            if (want > room) want = room > 1 ? room : 1;
+            if (lane < want) id = A.hlist[lbase + epos + (uint32_t)lane];
+            epos += (uint32_t)want;
+        }
         const bool have = lane < want;
-        bool leaf = false, opn = false;
+        bool leaf = false, opn = false, keep = false;
         uint32_t first = 0, count = 0, child = 0, nch = 0;
         if (have) {
             const double *bx = A.aabb + id;
@@ -796,14 +831,21 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
                               gap_box(blo[2], bhi[2], bx[2 * nm], bx[5 * nm]));
             const Node &nd = A.node[id];
             nch = nd.meta & 255u;
-            bool close = D2 < pad2;
-            leaf = close && nch == 0;
-            opn = close && nch != 0;
+            leaf = D2 < pad2 && nch == 0;
+            opn = D2 < padw2 && nch != 0;
+            keep = !opn;
             first = nd.first;
             count = nd.count;
             child = nd.child;
         }
-        uint64_t m = __ballot(leaf);
+        uint64_t m;
+        if constexpr (record) {
+            m = __ballot(keep);
+            const uint32_t pos = hl + (uint32_t)__popcll(m & lt);
+            if (keep && pos < lcap) A.hlist[lbase + pos] = id;
+            hl += (uint32_t)__popcll(m);
+        }
+        m = __ballot(leaf);
         if (leaf) {
             int o = kHardEnt - 1 - (nl + __popcll(m & lt));
             S.efirst[o] = first;
@@ -837,12 +879,16 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
     // work measure for the dispatch order: a pair-loop trip costs about seven
     // candidate tests
     if (A.cost && lane == 0) A.cost[grp] = cand + 7u * trips;
+    if constexpr (record) {
+        if (lane == 0) A.hlen[grp] = hl <= lcap ? hl : kNoList;
+    }
     if (lane == 0) {
         atomicAdd(&A.tally[tally_slot() + 1], (unsigned long long)ns * cand);
         atomicAdd(&A.tally[tally_slot() + 2], (unsigned long long)ngb_sum);
     }
 }
 
+template <int MODE>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_hard(ForceArgs A) {
     __shared__ HardLDS S;
     const uint32_t ng = *A.ng;
@@ -850,13 +896,16 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const uint32_t pos = sched_group(idx, ng);
         const uint32_t grp = A.order ? A.order[pos] : pos;
         HT_CHECK(grp < ng);
-        hard_group(A, S, grp);
+        hard_group<MODE>(A, S, grp);
     }
 }
 
 void launch_hard(const ForceArgs &A, int n_wg, hipStream_t s) {
     HT_CHECK(n_wg > 0 && n_wg % 8 == 0);
-    hipLaunchKernelGGL(k_hard, dim3((unsigned)n_wg), dim3(64), 0, s, A);
+    const dim3 grid((unsigned)n_wg), block(64);
+    if (A.hmode == 1) hipLaunchKernelGGL(k_hard<1>, grid, block, 0, s, A);
+    else if (A.hmode == 2) hipLaunchKernelGGL(k_hard<2>, grid, block, 0, s, A);
+    else hipLaunchKernelGGL(k_hard<0>, grid, block, 0, s, A);
 }
 
 }  // namespace htree

@@ -30,6 +30,14 @@
 namespace htree {
 
 constexpr int kMaxLevel = 21;          // 63-bit keys: 21 levels of 3 bits
+// Recorded hard searches (reused on the hard substeps between builds): the
+// search radius is widened by kHardSkin R2, and a group of ns sinks starting
+// at sorted position b0 keeps up to kListPerSink * ns node ids at
+// kListPerSink * b0; a longer list is not kept (the group then walks from
+// the root every time).
+constexpr double kHardSkin = 0.25;
+constexpr uint32_t kListPerSink = 24;
+constexpr uint32_t kNoList = 0xffffffffu;
 constexpr int kWave = 64;
 
 // Build frame of one system, written by the bounding-box kernels.
@@ -38,6 +46,7 @@ struct Frame {
     double side;        // root cube side, a power of two >= extent
     double scale;       // 2^21 / side (exact power of two)
     double R2pad2;      // (R2 + slack)^2 for conservative neighbour pruning
+    double R2rec2;      // (R2 (1 + kHardSkin) + slack)^2: radius of a recorded hard search
 };
 
 // Per-system build parameters (device table).
@@ -227,6 +236,8 @@ struct BuildBufs {
     uint32_t *hkey;        // [2n] sort keys (descending cost buckets)
     uint32_t *hval;        // [2n] group indices before the sort
     uint32_t *horder;      // [n] dispatch position -> hard group
+    uint32_t *hlist;       // [kListPerSink * n] recorded hard search lists (node ids)
+    uint32_t *hlen;        // [n] their lengths per hard group, or kNoList
     uint32_t *sorder;      // [2n] dispatch position -> soft group (first ng entries)
     uint32_t *ndisp;       // device count of the dispatch sort (ng + nhg)
 };
@@ -270,6 +281,9 @@ struct ForceArgs {
     const Frame *frame;       // [S]
     const uint32_t *order;    // null, or dispatch position -> group (a permutation)
     uint32_t *cost;           // null, or [ng] per-group work measure written by the hard kernel
+    uint32_t *hlist;          // hard kernel: recorded search lists (see kListPerSink)
+    uint32_t *hlen;           // hard kernel: their lengths per group
+    int32_t hmode;            // hard kernel: 0 walk from the root, 1 record, 2 replay
     uint32_t *wsoft;          // null, or [n]: each soft group writes its work measure to its sinks
     int64_t n;
     float *acc;               // [3][n] sorted order output

@@ -60,6 +60,9 @@ def lib():
         L.htree_soft_force.argtypes = [_p, _p, _p]
         L.htree_hard_force.argtypes = [_p, _p, _p]
         L.htree_step.argtypes = [_p, C.c_int32]
+        L.htree_kick_drift.argtypes = [_p, C.c_double, _p, C.c_double]
+        L.htree_refit.argtypes = [_p]
+        L.htree_get_state.argtypes = [_p, _p, _p]
         L.htree_sync.argtypes = [_p]
         L.htree_stats.argtypes = [_p, C.POINTER(_abi.Counters)]
         L.htree_group_counts.argtypes = [_p, _p, _p, _p]
@@ -118,6 +121,18 @@ class EmuTree:
         ngb = np.zeros(self.n, np.int32)
         self._check(lib().htree_hard_force(self._h, _ptr(a), _ptr(ngb)))
         return a, ngb
+
+    def kick_drift(self, dt_kick, dt_drift):
+        self._check(lib().htree_kick_drift(self._h, float(dt_kick), None, float(dt_drift)))
+
+    def refit(self):
+        self._check(lib().htree_refit(self._h))
+
+    def get_state(self):
+        x = np.zeros((3, self.n), np.float64)
+        v = np.zeros((3, self.n), np.float32)
+        self._check(lib().htree_get_state(self._h, _ptr(x), _ptr(v)))
+        return x, v
 
     def sync(self):
         self._check(lib().htree_sync(self._h))

@@ -92,3 +92,26 @@ def test_hard_kernel_emulated(orc, emu, name):
     e = _rel(ah.astype(np.float64), oah)[ongb > 0]
     assert np.percentile(e, 99) <= TOL_P99
     assert np.all(ah[:, ongb == 0] == 0)
+
+
+@pytest.mark.parametrize("name", ["plummer4k", "dups_lognormal"])
+def test_hard_search_replay_emulated(orc, emu, name):
+    """The hard searches recorded at the first launch after a build are
+    replayed after drifts and refits (no rebuild): the neighbour sets must
+    stay exact at the drifted positions."""
+    x, v, m, eps, R1, R2, G = _case(name)
+    m32 = m.astype(np.float32)
+    m64 = m32.astype(np.float64)
+    t = emu.EmuTree(x, v.astype(np.float32), m32, G=G, eps=eps, R1=R1, R2=R2, flags=4)
+    t.build_tree()
+    t.hard_force()          # records (flags = 4: reuse of the hard search)
+    for _ in range(3):
+        t.kick_drift(0.0, 0.15)   # about 0.2 R2 per drift at the typical speed
+        t.refit()
+        ah, ngb = t.hard_force()  # replays
+        xd, _ = t.get_state()
+        t.sync()
+        oah, _, ongb = orc.split_direct(xd, m64, G, eps, R1, R2, soft=False)
+        assert np.array_equal(ngb.astype(np.int64), ongb)
+        e = _rel(ah.astype(np.float64), oah)[ongb > 0]
+        assert np.percentile(e, 99) <= TOL_P99

@@ -230,3 +230,33 @@ def test_soft_force_fp64(orc, name, hybrid):
     assert e.max() <= 1e-7
     ep = np.abs(pot.cpu().numpy() - opot) / np.abs(opot)
     assert ep.max() <= 1e-7
+
+
+@pytest.mark.parametrize("name,G", [("plummer4k", 1.0), ("dups_lognormal", 2.5)])
+@pytest.mark.parametrize("reuse", [0, 1])
+def test_hard_force_after_refits(orc, name, G, reuse):
+    """Hard substeps without rebuilds: after each drift the node boxes are
+    refitted; the walk starts from the root, or (reuse) the search recorded
+    at the first launch after the build is replayed against them.  Neighbour counts must equal the brute-force
+    oracle's at the drifted positions after every substep, forces within the
+    tolerance."""
+    torch, P = need_gpu()
+    (x, v, m), eps, R1, R2 = _wl(name)
+    x, v32, m32, v64, m64 = as_inputs(x, v, m)
+    print("hard after refits", name, "reuse", reuse, flush=True)
+    t = make_tree(P, torch, x, v32, m32, G=G, eps=eps, R1=R1, R2=R2,
+                  flags=P.F_REUSE if reuse else 0)
+    t.build_tree()
+    t.hard_force()
+    for k in range(3):
+        t.kick_drift(0.0, dt_drift=0.15)   # about 0.2 R2 per drift at the typical speed
+        t.refit()
+        ah, ngb = t.hard_force()
+        xd, _ = t.get_state()
+        t.sync()
+        xd = xd.cpu().numpy()
+        oah, _, ongb = orc.split_direct(xd, m64, G, eps, R1, R2, soft=False)
+        assert np.array_equal(ngb.cpu().numpy().astype(np.int64), ongb)
+        e = rel_err(ah.cpu().numpy().astype(np.float64), oah)
+        report("hard after refit %d" % k, e[ongb > 0])
+        assert np.percentile(e[ongb > 0], 99) <= TOL_P99

@@ -102,3 +102,37 @@ def test_energy_error_reported(orc):
     eo = sum(orc.energy(xo, vo, m64, 1.0, wl.eps))
     print("relative energy error: gpu %.3e oracle %.3e" % ((eg - e0) / abs(e0), (eo - e0) / abs(e0)))
     assert abs(eg - eo) / abs(e0) < 1e-6
+
+
+def test_energy_sweep_small():
+    """The (n, R1, R2) energy-error sweep of the paper's parameter selection
+    (section IV.A), small: every setting runs and conserves energy to a
+    sane level.  The paper prints no energy errors: the values are reported
+    (parity unpinned); the energy itself is the GPU direct-sum potential,
+    checked against the oracle's in test_energy_direct_matches_oracle."""
+    torch, P = need_gpu()
+    from paper_1406_6158_amd import sweep
+    wl = synth.WORKLOADS["plummer4k"]
+    x, v, m = wl.make()
+    rows = sweep.sweep(x, v, m.astype(np.float32), wl.eps, wl.theta, 1.0 / 128, 1.0 / 8, [1, 2, 4],
+                       [32.0, 64.0], lambda k: synth.r2_for_neighbours("plummer", 4096, k))
+    for r in rows:
+        print("sweep n_sub %d ngb %s hybrid %d: dE/E %.3e" % (r["n_sub"], r.get("ngb"), r["hybrid"],
+                                                           r["dE_rel"]), flush=True)
+        assert np.isfinite(r["dE_rel"]) and abs(r["dE_rel"]) < 1e-3
+    assert len(rows) == 7
+
+
+def test_energy_direct_matches_oracle(orc):
+    """The sweep's energy (GPU direct-sum potential, FP64 reductions) against
+    the oracle's FP64 direct energy of the same state."""
+    torch, P = need_gpu()
+    from paper_1406_6158_amd import sweep
+    wl = synth.WORKLOADS["plummer4k"]
+    x, v, m = wl.make()
+    x, v32, m32, v64, m64 = as_inputs(x, v, m)
+    kin, pe = sweep.total_energy(torch.from_numpy(x).cuda(), torch.from_numpy(v32).cuda(),
+                                 torch.from_numpy(m32).cuda(), 1.0, wl.eps)
+    okin, ope = orc.energy(x, v64, m64, 1.0, wl.eps)
+    assert abs(kin - okin) <= 1e-12 * abs(okin)
+    assert abs(pe - ope) <= 1e-6 * abs(ope)
