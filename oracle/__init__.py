@@ -61,6 +61,8 @@ def lib():
         L.orc_tree_frame.argtypes = [_p, _p, _p]
         L.orc_tree_sorted.argtypes = [_p, _p, _p, _p]
         L.orc_tree_nodes.argtypes = [_p] * 11
+        L.orc_tree_set_mac.argtypes = [_p, _f64, _f64, _i32]
+        L.orc_tree_node_mac.argtypes = [_p, _p, _p]
         L.orc_tree_groups.restype = _i64
         L.orc_tree_groups.argtypes = [_p, _i32, _i32]
         L.orc_tree_group_starts.argtypes = [_p, _p]
@@ -187,6 +189,21 @@ class Tree:
                                         ("level", "first", "count", "parent", "nchild", "M",
                                          "com", "blo", "l", "rb2")])
         return d
+
+    def set_mac(self, a_err=0.0, G=1.0, min_sinks=False):
+        """Opening radii by the paper's absolute MAC (a_err > 0, section II.B)
+        or l / theta (a_err = 0); groups measure cells by the minimum over
+        their sinks (min_sinks) or by their bounding box."""
+        lib().orc_tree_set_mac(self._h, float(a_err), float(G), int(bool(min_sinks)))
+        return self
+
+    def node_mac(self):
+        """(B2, bmax2) of every node, in the order of nodes()."""
+        nn = self.nnodes
+        B2 = np.zeros(nn)
+        bm = np.zeros(nn)
+        lib().orc_tree_node_mac(self._h, _ptr(B2), _ptr(bm))
+        return B2, bm
 
     def group_starts(self):
         """Start of each sink group in sorted order, plus n at the end."""

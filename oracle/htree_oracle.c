@@ -23,10 +23,11 @@
  *  - a cell is split iff it holds at least n_crit particles and is above
  *    level 21 (63-bit keys); the root is the power-of-two cube anchored at the
  *    coordinate minimum;
- *  - the opening radius is r_b = l / theta (cell side l) in place of the
- *    absolute MAC, with the paper's "open iff r_b > r" rule;
+ *  - the opening radius is r_b = l / theta (cell side l) by default, or the
+ *    paper's absolute MAC of section II.B (orc_tree_set_mac) with G kept in
+ *    sqrt(3 G B2 / a_err); either way the paper's "open iff r_b > r" rule;
  *  - a sink group uses the distance from its bounding box, a lower bound of
- *    the paper's minimum over sinks;
+ *    the paper's minimum over sinks, or (orc_tree_set_mac) that minimum;
  *  - in hybrid mode a cell is accepted only if every pair it stands for is
  *    at r >= R2; leaves nearer than that are summed particle by particle with
  *    the (1 - K) weight;
@@ -47,7 +48,7 @@
 
 #define ORC_MAXLEVEL 21
 
-int orc_version(void) { return 3; }
+int orc_version(void) { return 4; }
 
 int orc_threads(void)
 {
@@ -240,6 +241,8 @@ typedef struct {
     double blo[3];            /* cell box lower corner, build frame        */
     double l;                 /* cell side                                 */
     double rb2;               /* squared opening radius                    */
+    double B2;                /* sum of m |COM - u|^2 over the cell (eq. 6) */
+    double bmax2;             /* max |COM - u|^2 over the cell's particles  */
 } onode;
 
 typedef struct {
@@ -258,6 +261,7 @@ typedef struct {
     int64_t *gstart;          /* sink groups: [gstart[k], gstart[k+1]) in sorted order */
     int64_t ng, gcap;
     int32_t g;
+    int32_t mac_min;          /* group rule: 0 box distance, 1 minimum over sinks */
 } orc_tree;
 
 typedef struct { uint64_t key; int64_t idx; } kv;
@@ -392,6 +396,13 @@ static int64_t split(orc_tree *T, int32_t lev, int64_t b, int64_t e, int64_t par
  * Geometry: l = side 2^-level; box lower corner = (q >> (21 - level)) l;
  * squared opening radius r_b^2 = (l l) invtheta^2 with invtheta^2 = 1/theta^2.
  */
+/* |p - q|^2 as fma(dz, dz, fma(dy, dy, dx * dx)), d = p - q. */
+static inline double sqdist(const double *p, double qx, double qy, double qz)
+{
+    double dx = p[0] - qx, dy = p[1] - qy, dz = p[2] - qz;
+    return fma(dz, dz, fma(dy, dy, dx * dx));
+}
+
 static void moments(orc_tree *T, int64_t id, double *Sout)
 {
     onode *c = &T->nd[id];
@@ -419,6 +430,31 @@ static void moments(orc_tree *T, int64_t id, double *Sout)
         Sout[a] = S[a];
         c->com[a] = (M != 0.0) ? S[a] / M : c->blo[a] + 0.5 * c->l;
     }
+    /* Quantities of the absolute MAC (section II.B, eqs. 5-6), in the build
+     * frame.  B2 = sum_i m_i |COM - u_i|^2: a leaf sums its particles in
+     * sorted order; an inner cell sums over its children in octant order
+     * B2_c + M_c |COM - COM_c|^2 (the parallel-axis identity, equal to the
+     * particle sum up to rounding).  bmax2 = max_i |COM - u_i|^2 over all the
+     * cell's particles (a maximum: independent of order). */
+    double B2 = 0.0, bm = 0.0;
+    if (c->nchild == 0) {
+        for (int64_t i = c->first; i < c->first + c->count; i++) {
+            double q = sqdist(c->com, T->u[i], T->u[n + i], T->u[2 * n + i]);
+            B2 = fma(T->m[i], q, B2);
+        }
+    } else {
+        for (int k = 0; k < c->nchild; k++) {
+            const onode *h = &T->nd[c->child[k]];
+            double q = sqdist(c->com, h->com[0], h->com[1], h->com[2]);
+            B2 = B2 + fma(h->M, q, h->B2);
+        }
+    }
+    for (int64_t i = c->first; i < c->first + c->count; i++) {
+        double q = sqdist(c->com, T->u[i], T->u[n + i], T->u[2 * n + i]);
+        if (q > bm) bm = q;
+    }
+    c->B2 = B2;
+    c->bmax2 = bm;
 }
 
 orc_tree *orc_tree_build(int64_t n, const double *x, const double *m, int32_t n_crit, double theta)
@@ -491,6 +527,41 @@ void orc_tree_nodes(const orc_tree *T, int32_t *level, int64_t *first, int64_t *
     }
 }
 
+/*
+ * Opening radii and group rule (section II.B eq. 5, section III.A.2 eq. 11).
+ * a_err > 0: the absolute MAC,
+ *   r_b = b_max / 2 + sqrt(b_max^2 / 4 + sqrt(3 G B2 / a_err)),
+ * evaluated as b = sqrt(bmax2), t = sqrt(((3 G) B2) / a_err),
+ * r_b = 0.5 b + sqrt(0.25 bmax2 + t), rb2 = r_b * r_b (every sqrt correctly
+ * rounded); a_err = 0: r_b = l / theta of the build.  min_sinks = 1: a group
+ * measures a cell by the minimum over its sinks of |u_i - COM|^2 (the paper's
+ * n_vec rule) instead of the distance from its bounding box.
+ */
+void orc_tree_set_mac(orc_tree *T, double a_err, double G, int32_t min_sinks)
+{
+    T->mac_min = min_sinks ? 1 : 0;
+    for (int64_t k = 0; k < T->nn; k++) {
+        onode *c = &T->nd[k];
+        if (a_err > 0.0) {
+            double b = sqrt(c->bmax2);
+            double t = sqrt(((3.0 * G) * c->B2) / a_err);
+            double rb = 0.5 * b + sqrt(0.25 * c->bmax2 + t);
+            c->rb2 = rb * rb;
+        } else {
+            c->rb2 = (c->l * c->l) * T->invth2;
+        }
+    }
+}
+
+/* B2 and bmax2 of every node, in the order of orc_tree_nodes. */
+void orc_tree_node_mac(const orc_tree *T, double *B2, double *bmax2)
+{
+    for (int64_t k = 0; k < T->nn; k++) {
+        if (B2) B2[k] = T->nd[k].B2;
+        if (bmax2) bmax2[k] = T->nd[k].bmax2;
+    }
+}
+
 /* ===========================================================================
  * Sink groups (section III.A.2: several sinks share one traversal; their
  * positions must be close, which the key order provides)
@@ -546,6 +617,7 @@ void orc_tree_group_starts(const orc_tree *T, int64_t *starts)
 
 typedef struct {
     double lo[3], hi[3];      /* sink-group bounding box, build frame */
+    int64_t b, e;             /* the group's sinks (sorted positions)  */
 } gbox;
 
 static inline double gap_pt(double lo, double hi, double p)
@@ -568,6 +640,8 @@ static inline double d2(double gx, double gy, double gz)
 static void group_box(const orc_tree *T, int64_t b, int64_t e, gbox *B)
 {
     int64_t n = T->n;
+    B->b = b;
+    B->e = e;
     for (int a = 0; a < 3; a++) {
         double lo = T->u[a * n + b], hi = lo;
         for (int64_t i = b + 1; i < e; i++) {
@@ -597,7 +671,8 @@ static void push(int64_t **a, int64_t *n, int64_t *cap, int64_t v)
 
 /*
  * Opening rule for a sink group and a cell c (the paper opens when r_b > r):
- *   D1 = dist^2(box_g, COM_c),  D2 = dist^2(box_g, box_c)   (fma form above)
+ *   D1 = dist^2(box_g, COM_c) (or, with min_sinks, min_i |u_i - COM_c|^2),
+ *   D2 = dist^2(box_g, box_c)   (fma form above)
  *   accepted iff D1 >= r_b^2 and (hybrid ? D2 >= R2^2 : D2 > 0);
  * an accepted cell is one particle-cell term; a rejected leaf contributes its
  * particles ("near" iff hybrid and D2 < R2^2, else "far"); otherwise the
@@ -606,9 +681,20 @@ static void push(int64_t **a, int64_t *n, int64_t *cap, int64_t v)
 static void walk(const orc_tree *T, int64_t id, const gbox *B, double R2sq, int hybrid, wlist *L)
 {
     const onode *c = &T->nd[id];
-    double D1 = d2(gap_pt(B->lo[0], B->hi[0], c->com[0]),
-                   gap_pt(B->lo[1], B->hi[1], c->com[1]),
-                   gap_pt(B->lo[2], B->hi[2], c->com[2]));
+    double D1;
+    if (T->mac_min) {
+        /* minimum over the group's sinks of |u_i - COM|^2 */
+        int64_t n = T->n;
+        D1 = INFINITY;
+        for (int64_t i = B->b; i < B->e; i++) {
+            double q = sqdist(c->com, T->u[i], T->u[n + i], T->u[2 * n + i]);
+            if (q < D1) D1 = q;
+        }
+    } else {
+        D1 = d2(gap_pt(B->lo[0], B->hi[0], c->com[0]),
+                gap_pt(B->lo[1], B->hi[1], c->com[1]),
+                gap_pt(B->lo[2], B->hi[2], c->com[2]));
+    }
     double D2 = d2(gap_box(B->lo[0], B->hi[0], c->blo[0], c->blo[0] + c->l),
                    gap_box(B->lo[1], B->hi[1], c->blo[1], c->blo[1] + c->l),
                    gap_box(B->lo[2], B->hi[2], c->blo[2], c->blo[2] + c->l));
