@@ -75,6 +75,13 @@ typedef struct {
                           /* at most group_cell * group_size particles whose parent */
                           /* holds more, and the leaves whose parent holds more;    */
                           /* each is cut into chunks of group_size (1..4096)        */
+    int32_t group_mac;    /* how a sink group measures a cell for the opening test:  */
+                          /* 0 the distance from the group's bounding box to the    */
+                          /* centre of mass; 1 the minimum over the group's sinks   */
+                          /* of their distance to it (section III.A.2, eq. 11)      */
+    double  a_err;        /* 0: opening radius l / theta; > 0: the absolute MAC of   */
+                          /* section II.B (eqs. 5-6), r_b = b_max/2 + sqrt(b_max^2/4 */
+                          /* + sqrt(3 G B2 / a_err)), theta then unused             */
 } htree_params;
 
 typedef struct {
@@ -93,7 +100,7 @@ typedef struct htree_ctx htree_ctx;
 
 /* Defaults: G = 1, eps = 0.01, theta = 0.5, R1 = 0.05, R2 = 0.1, dt_soft = 1/16,
  * n_sub = 4, hybrid = 1, n_crit = 16, group_size = 64, precision = 0, flags = 0,
- * group_cell = 16. */
+ * group_cell = 16, group_mac = 0, a_err = 0. */
 void htree_default_params(htree_params *p);
 
 /* Exact number of workspace bytes a context for n particles needs (0 if the
@@ -209,6 +216,15 @@ htree_status htree_sync(htree_ctx *ctx);
  * fields are the summed HIP-event times of each phase on the context's
  * stream.  Synchronises the stream. */
 htree_status htree_stats(htree_ctx *ctx, htree_counters *out);
+
+/* Opening-test quantities of the last build's nodes, in the order of
+ * htree_export_nodes (host arrays, any may be NULL): B2 = sum m |COM - u|^2
+ * (a leaf over its particles in sorted order, an inner node as the sum over
+ * its children of B2_c + M_c |COM - COM_c|^2), bmax2 = the largest
+ * |COM - u|^2 over the node's particles, and the squared opening radius rb2.
+ * B2 and bmax2 are computed only when some system has a_err > 0 (else 0).
+ * Synchronises the stream. */
+htree_status htree_export_node_mac(htree_ctx *ctx, double *B2, double *bmax2, double *rb2);
 
 /* Sink groups of the last build (section III.A.2: sinks that share one
  * traversal).  A group holds at most group_size particles inside one tree

@@ -215,3 +215,13 @@ class HTree:
         check(lib().htree_export_nodes(self._h, *[C.c_void_p(d[k].ctypes.data) for k in
                                                   ("level", "first", "count", "M", "com")]))
         return d
+
+    def export_node_mac(self):
+        """(B2, bmax2, rb2) of the last build's nodes, in export_nodes order."""
+        import numpy as np
+        nn = int(lib().htree_node_count(self._h))
+        if nn < 0:
+            check(-3)
+        a = [np.zeros(nn) for _ in range(3)]
+        check(lib().htree_export_node_mac(self._h, *[C.c_void_p(v.ctypes.data) for v in a]))
+        return tuple(a)

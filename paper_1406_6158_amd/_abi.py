@@ -37,7 +37,7 @@ class Params(C.Structure):
                 ("R1", C.c_double), ("R2", C.c_double), ("dt_soft", C.c_double),
                 ("n_sub", C.c_int32), ("hybrid", C.c_int32), ("n_crit", C.c_int32),
                 ("group_size", C.c_int32), ("precision", C.c_int32), ("flags", C.c_int32),
-                ("group_cell", C.c_int32)]
+                ("group_cell", C.c_int32), ("group_mac", C.c_int32), ("a_err", C.c_double)]
 
 
 class Counters(C.Structure):
@@ -115,6 +115,7 @@ def lib() -> C.CDLL:
     L.htree_node_count.argtypes = [_p]
     L.htree_node_count.restype = C.c_int64
     L.htree_export_nodes.argtypes = [_p, _p, _p, _p, _p, _p]
+    L.htree_export_node_mac.argtypes = [_p, _p, _p, _p]
     L.htree_group_count.argtypes = [_p]
     L.htree_group_count.restype = C.c_int64
     L.htree_export_groups.argtypes = [_p, _p]
@@ -140,7 +141,7 @@ def lib() -> C.CDLL:
     for name in ("htree_create", "htree_create_static", "htree_batch_create", "htree_set_state", "htree_build_tree", "htree_soft_force",
                  "htree_hard_force", "htree_kick_drift", "htree_step", "htree_refit", "htree_get_state",
                  "htree_sync", "htree_stats", "htree_group_counts", "htree_export_keys",
-                 "htree_export_nodes", "htree_export_groups"):
+                 "htree_export_nodes", "htree_export_node_mac", "htree_export_groups"):
         getattr(L, name).restype = _st
     _lib = L
     return L

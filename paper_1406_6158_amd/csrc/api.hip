@@ -74,6 +74,9 @@ htree_status validate_one(const htree_params *p, int64_t n) {
         return fail(HTREE_EINVAL, "unknown flags");
     if (p->group_cell < 1 || p->group_cell > 4096)
         return fail(HTREE_EINVAL, "group_cell must be in [1, 4096]");
+    if (p->group_mac != 0 && p->group_mac != 1)
+        return fail(HTREE_EINVAL, "group_mac must be 0 (box distance) or 1 (minimum over sinks)");
+    if (!is_fin(p->a_err) || p->a_err < 0) return fail(HTREE_EINVAL, "a_err must be >= 0");
     return HTREE_OK;
 }
 
@@ -87,9 +90,9 @@ htree_status validate(const htree_params *p, const int64_t *n, int32_t S) {
         if (st) return st;
         const htree_params &a = p[0], &b = p[s];
         if (b.dt_soft != a.dt_soft || b.n_sub != a.n_sub || b.hybrid != a.hybrid ||
-            b.precision != a.precision || b.flags != a.flags)
-            return fail(HTREE_EINVAL, "system %d: dt_soft, n_sub, hybrid, precision and flags "
-                                      "must equal those of system 0", s);
+            b.precision != a.precision || b.flags != a.flags || b.group_mac != a.group_mac)
+            return fail(HTREE_EINVAL, "system %d: dt_soft, n_sub, hybrid, precision, flags and "
+                                      "group_mac must equal those of system 0", s);
         tot += n[s];
     }
     if (tot > kMaxN) return fail(HTREE_EINVAL, "total particles %lld exceed 2^27", (long long)tot);
@@ -164,6 +167,8 @@ void carve(Carver &C, htree_ctx *c) {
     B.sysbits = 0;
     while ((1 << B.sysbits) < S) B.sysbits++;
     B.max_n_crit = 0;
+    B.abs_mac = false;
+    for (int32_t s = 0; s < S; s++) B.abs_mac |= c->ps[s].a_err > 0.0;
     B.nchunks = chunk_count(c->ns);
     B.nnmax = 0;
     for (int32_t s = 0; s < S; s++) {
@@ -204,9 +209,14 @@ void carve(Carver &C, htree_ctx *c) {
     B.cpl = C.take<int8_t>(n);
     B.leaflev = C.take<int8_t>(n);
     B.nstart = C.take<uint32_t>(n + 1);
+    // partials of the largest scan: n + 1 flags, the sort histograms, and
+    // (absolute MAC) the nnmax + 1 chunk counts of the b_max pass
     int64_t sp = (int64_t)scan_partials(n + 1);
     int64_t sp2 = (int64_t)scan_partials(256 * sort_blocks(nsort));
-    B.scan_part = C.take<uint32_t>(sp > sp2 ? sp : sp2);
+    int64_t sp3 = B.abs_mac ? (int64_t)scan_partials(nnmax + 1) : 0;
+    if (sp2 > sp) sp = sp2;
+    if (sp3 > sp) sp = sp3;
+    B.scan_part = C.take<uint32_t>(sp);
     B.nn = C.take<uint32_t>(4);
     B.pre_key = C.take<uint32_t>(nnmax);
     B.pre_val = C.take<uint32_t>(nnmax);
@@ -222,6 +232,9 @@ void carve(Carver &C, htree_ctx *c) {
         B.ptmp_k = B.ptmp_v = nullptr;
     }
     B.node = C.take<Node>(nnmax);
+    B.B2 = C.take<double>(B.abs_mac ? nnmax : 1);
+    B.bmax = C.take<unsigned long long>(B.abs_mac ? nnmax : 1);
+    B.bitems = C.take<uint32_t>(B.abs_mac ? nnmax + 1 : 1);
     B.S3 = C.take<double>(3 * nnmax);
     B.aabb = C.take<double>(6 * nnmax);
     {
@@ -296,6 +309,8 @@ htree_status upload_tables(htree_ctx *c) {
         y.g = (uint32_t)q.group_size;
         y.gcell = (uint32_t)q.group_cell;
         y.invth2 = 1.0 / (q.theta * q.theta);
+        y.aerr = q.a_err;
+        y.G = q.G;
         y.R2 = q.hybrid ? q.R2 : 0.0;
         SysF &f = sysf[s];
         f.G = (float)q.G;
@@ -414,7 +429,8 @@ htree_status do_soft(htree_ctx *c) {
     A.order = c->B.sorder;
     A.wsoft = c->B.wsoft[c->B.cur];
     ev_begin(c, 1);
-    launch_soft(A, c->p.hybrid != 0, pot, c->p.precision, c->n_wg, c->stream);
+    launch_soft(A, c->p.hybrid != 0, pot, c->p.precision, c->p.group_mac != 0, c->n_wg,
+                c->stream);
     ev_end(c, 1);
     HIP_OK(hipGetLastError());
     c->have_soft = true;
@@ -517,6 +533,8 @@ void htree_default_params(htree_params *p) {
     p->precision = 0;
     p->flags = 0;
     p->group_cell = 16;
+    p->group_mac = 0;
+    p->a_err = 0.0;
 }
 
 size_t htree_batch_workspace_bytes(const htree_params *p, const int64_t *n, int32_t S) {
@@ -868,6 +886,34 @@ htree_status htree_export_nodes(htree_ctx *c, int32_t *level, int32_t *first, in
         if (mass) mass[k] = h[k].M;
         if (com)
             for (int a = 0; a < 3; a++) com[a * nn + k] = h[k].com[a];
+    }
+    return HTREE_OK;
+}
+
+htree_status htree_export_node_mac(htree_ctx *c, double *B2, double *bmax2, double *rb2) {
+    CTX_CHECK(c);
+    if (!c->tree) return fail(HTREE_ESTATE, "no current tree");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    uint32_t nn = 0;
+    HIP_OK(hipMemcpy(&nn, c->B.nn, sizeof nn, hipMemcpyDeviceToHost));
+    if (B2 || bmax2) {
+        if (c->B.abs_mac) {
+            std::vector<unsigned long long> bits(nn);
+            if (B2) HIP_OK(hipMemcpy(B2, c->B.B2, sizeof(double) * nn, hipMemcpyDeviceToHost));
+            if (bmax2) {
+                HIP_OK(hipMemcpy(bits.data(), c->B.bmax, sizeof(unsigned long long) * nn,
+                                 hipMemcpyDeviceToHost));
+                memcpy(bmax2, bits.data(), sizeof(double) * nn);
+            }
+        } else {
+            if (B2) memset(B2, 0, sizeof(double) * nn);
+            if (bmax2) memset(bmax2, 0, sizeof(double) * nn);
+        }
+    }
+    if (rb2) {
+        std::vector<Node> h(nn);
+        HIP_OK(hipMemcpy(h.data(), c->B.node, sizeof(Node) * nn, hipMemcpyDeviceToHost));
+        for (uint32_t k = 0; k < nn; k++) rb2[k] = h[k].rb2;
     }
     return HTREE_OK;
 }

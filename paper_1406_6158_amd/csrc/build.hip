@@ -702,16 +702,26 @@ __global__ __launch_bounds__(256) void k_level_starts(const uint32_t *lkey, int 
         for (uint32_t m = l + 1; m <= (uint32_t)kMaxLevel + 1; m++) lstart[m] = nn;
 }
 
+// |p - q|^2 as fma(dz, dz, fma(dy, dy, dx * dx)) with d = p - q.
+__device__ inline double sqdist(const double *p, double qx, double qy, double qz) {
+    const double dx = p[0] - qx, dy = p[1] - qy, dz = p[2] - qz;
+    return fma(dz, dz, fma(dy, dy, dx * dx));
+}
+
 // One level of the bottom-up pass, deepest level first.  Every node gets the
 // box of its particles' master positions (exact minima and maxima: a leaf
 // over its particles, an internal node over its children's boxes).  With
 // MOM, also the moments: a leaf sums its particles in sorted order (M += m,
 // S = fma(m, u, S)); an internal node sums its children's M and S in octant
-// order; COM = S / M.
-template <bool MOM>
+// order; COM = S / M.  With MAC (absolute MAC, section II.B eq. 6), also
+// B2 = sum m |COM - u|^2: a leaf over its particles in sorted order
+// (B2 = fma(m, |COM - u|^2, B2)), an internal node over its children in
+// octant order (B2 += fma(M_c, |COM - COM_c|^2, B2_c), the parallel-axis
+// identity).
+template <bool MOM, bool MAC>
 __global__ __launch_bounds__(256) void k_level_pass(Node *node, const double4 *src, const double *x,
                                                     int64_t n, double *S3, double *aabb,
-                                                    const uint32_t *lstart, int level,
+                                                    double *B2v, const uint32_t *lstart, int level,
                                                     int64_t nnmax) {
     const uint32_t b0 = lstart[level], b1 = lstart[level + 1];
     for (uint32_t b = b0 + blockIdx.x * 256 + threadIdx.x; b < b1; b += gridDim.x * 256) {
@@ -758,7 +768,106 @@ __global__ __launch_bounds__(256) void k_level_pass(Node *node, const double4 *s
                 N.com[a] = (M != 0.0) ? s[a] / M : N.blo[a] + 0.5 * N.l;
             }
         }
+        if (MAC) {
+            const double com[3] = {N.com[0], N.com[1], N.com[2]};
+            double B2 = 0.0;
+            if (nch == 0) {
+                for (uint32_t i = N.first; i < N.first + N.count; i++) {
+                    const double4 q = src[i];
+                    B2 = fma(q.w, sqdist(com, q.x, q.y, q.z), B2);
+                }
+            } else {
+                for (uint32_t k = 0; k < nch; k++) {
+                    const Node &C = node[N.child + k];
+                    B2 = B2 + fma(C.M, sqdist(com, C.com[0], C.com[1], C.com[2]), B2v[N.child + k]);
+                }
+            }
+            B2v[b] = B2;
+        }
     }
+}
+
+// b_max^2 = max |COM - u|^2 over a node's particles (a maximum, exact in
+// any order).  Nodes of at most kBmaxSmall particles are done by one thread
+// each; the others are cut into chunks of kBmaxChunk particles, one wave per
+// chunk, combined with atomic maxima on the bits of the (non-negative)
+// doubles.
+constexpr uint32_t kBmaxSmall = 256, kBmaxChunk = 4096;
+
+__global__ __launch_bounds__(256) void k_bmax_small(const Node *node, const uint32_t *nn_dev,
+                                                    const double4 *src, int64_t nnmax,
+                                                    unsigned long long *bmax, uint32_t *items) {
+    const uint32_t b = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t nn = *nn_dev;
+    if (b > (uint32_t)nnmax) return;
+    if (b >= nn) {
+        items[b] = 0u;       // the scan runs over nnmax + 1 entries
+        return;
+    }
+    const Node &N = node[b];
+    if (N.count > kBmaxSmall) {
+        items[b] = (N.count + kBmaxChunk - 1) / kBmaxChunk;
+        bmax[b] = 0ull;
+        return;
+    }
+    items[b] = 0u;
+    const double com[3] = {N.com[0], N.com[1], N.com[2]};
+    double m = 0.0;
+    for (uint32_t i = N.first; i < N.first + N.count; i++) {
+        const double4 q = src[i];
+        m = fmax(m, sqdist(com, q.x, q.y, q.z));
+    }
+    bmax[b] = (unsigned long long)__double_as_longlong(m);
+}
+
+// items holds the exclusive scan of the chunk counts; total their sum.
+__global__ __launch_bounds__(256) void k_bmax_big(const Node *node, const uint32_t *nn_dev,
+                                                  const double4 *src, const uint32_t *items,
+                                                  const uint32_t *total,
+                                                  unsigned long long *bmax) {
+    const uint32_t nn = *nn_dev, nw = *total;
+    const int lane = __lane_id();
+    for (uint32_t w = blockIdx.x * 4 + (threadIdx.x >> 6); w < nw; w += gridDim.x * 4) {
+        // the node owning work item w: the last with items[b] <= w (nodes
+        // without chunks share their offset with the next node, which has
+        // the chunks)
+        uint32_t lo = 0, hi = nn;      // items[lo] <= w < items[hi]
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (items[mid] <= w) lo = mid; else hi = mid;
+        }
+        const Node &N = node[lo];
+        const uint32_t k = w - items[lo];
+        const uint32_t i0 = N.first + k * kBmaxChunk;
+        const uint32_t e = N.first + N.count;
+        const uint32_t i1 = e < i0 + kBmaxChunk ? e : i0 + kBmaxChunk;
+        const double com[3] = {N.com[0], N.com[1], N.com[2]};
+        double m = 0.0;
+        for (uint32_t i = i0 + (uint32_t)lane; i < i1; i += 64) {
+            const double4 q = src[i];
+            m = fmax(m, sqdist(com, q.x, q.y, q.z));
+        }
+        m = wave_max(m);
+        if (lane == 0) atomicMax(&bmax[lo], (unsigned long long)__double_as_longlong(m));
+    }
+}
+
+// Absolute MAC (section II.B eq. 5) for the nodes of systems with a_err > 0:
+// b = sqrt(bmax2), t = sqrt(((3 G) B2) / a_err), r_b = 0.5 b + sqrt(0.25
+// bmax2 + t), rb2 = r_b * r_b; every sqrt and the division correctly
+// rounded.  Other systems keep l^2 / theta^2.
+__global__ __launch_bounds__(256) void k_abs_mac(Node *node, const uint32_t *nn_dev,
+                                                 const Sys *sys, const double *B2v,
+                                                 const unsigned long long *bmax) {
+    const uint32_t b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= *nn_dev) return;
+    Node &N = node[b];
+    const Sys &y = sys[N.sys];
+    if (!(y.aerr > 0.0)) return;
+    const double bm = __longlong_as_double((long long)bmax[b]);
+    const double t = sqrt(((3.0 * y.G) * B2v[b]) / y.aerr);
+    const double rb = 0.5 * sqrt(bm) + sqrt(0.25 * bm + t);
+    N.rb2 = rb * rb;
 }
 
 // Refit after a drift (same tree, same sorted order): node boxes directly
@@ -908,13 +1017,31 @@ void launch_levels(BuildBufs &B, bool moments, hipStream_t s) {
     unsigned gn = (unsigned)((B.nnmax + 255) / 256);
     unsigned gl = gn < 1024u ? gn : 1024u;
     const double *x = B.x[B.cur];
+    const bool mac = moments && B.abs_mac;
     for (int l = kMaxLevel; l >= 0; l--) {
-        if (moments)
-            hipLaunchKernelGGL(k_level_pass<true>, dim3(gl), dim3(256), 0, s, B.node, B.src, x,
-                               B.n, B.S3, B.aabb, B.lstart, l, B.nnmax);
+        if (mac)
+            hipLaunchKernelGGL((k_level_pass<true, true>), dim3(gl), dim3(256), 0, s, B.node,
+                               B.src, x, B.n, B.S3, B.aabb, B.B2, B.lstart, l, B.nnmax);
+        else if (moments)
+            hipLaunchKernelGGL((k_level_pass<true, false>), dim3(gl), dim3(256), 0, s, B.node,
+                               B.src, x, B.n, B.S3, B.aabb, B.B2, B.lstart, l, B.nnmax);
         else
-            hipLaunchKernelGGL(k_level_pass<false>, dim3(gl), dim3(256), 0, s, B.node, B.src, x,
-                               B.n, B.S3, B.aabb, B.lstart, l, B.nnmax);
+            hipLaunchKernelGGL((k_level_pass<false, false>), dim3(gl), dim3(256), 0, s, B.node,
+                               B.src, x, B.n, B.S3, B.aabb, B.B2, B.lstart, l, B.nnmax);
+    }
+    if (mac) {
+        // b_max^2, then the opening radii of the absolute MAC
+        const unsigned gi = (unsigned)((B.nnmax + 1 + 255) / 256);
+        hipLaunchKernelGGL(k_bmax_small, dim3(gi), dim3(256), 0, s, B.node, B.nn, B.src, B.nnmax,
+                           B.bmax, B.bitems);
+        launch_scan_u32(B.bitems, B.nnmax + 1, B.scan_part, B.nn + 2, s);
+        // chunks: at most n / kBmaxChunk per level plus one per big node
+        const int64_t most = (B.n / kBmaxChunk + 1) * (kMaxLevel + 1) + B.n / kBmaxSmall + 1;
+        const int64_t nb = (most + 3) / 4;
+        hipLaunchKernelGGL(k_bmax_big, dim3((unsigned)(nb < 8192 ? nb : 8192)), dim3(256), 0, s,
+                           B.node, B.nn, B.src, B.bitems, B.nn + 2, B.bmax);
+        hipLaunchKernelGGL(k_abs_mac, dim3(gn), dim3(256), 0, s, B.node, B.nn, B.sys, B.B2,
+                           B.bmax);
     }
 }
 

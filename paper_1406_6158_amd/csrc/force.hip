@@ -129,6 +129,14 @@ __device__ inline uint32_t sched_group(uint32_t idx, uint32_t ng) {
     return idx - r + (r % 8) * kRun + r / 8;
 }
 
+// Lane k's value of v (k wave-uniform), in scalar registers.
+__device__ inline double uniform_lane_f64(double v, int k) {
+    const uint64_t b = (uint64_t)__double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, k);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), k);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
 // A wave-uniform double held in scalar registers.
 __device__ inline double uniform_f64(double v) {
     const uint64_t b = (uint64_t)__double_as_longlong(v);
@@ -334,7 +342,7 @@ template <typename T> struct SoftConst;
 template <> struct SoftConst<float> : SoftConst32 { using SoftConst32::SoftConst32; };
 template <> struct SoftConst<double> : SoftConst64 { using SoftConst64::SoftConst64; };
 
-template <bool HYBRID, bool POT, typename T>
+template <bool HYBRID, bool POT, bool MINS, typename T>
 __device__ void soft_group(const ForceArgs &A, SoftLDS<T> &S, uint32_t grp) {
     const int lane = __lane_id();
     const uint64_t lt = lanemask_lt();
@@ -365,30 +373,51 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS<T> &S, uint32_t grp) {
         avail -= (uint32_t)want;
         const bool have = lane < want;
 
-        bool acc_c = false, leaf = false, opn = false, nr = false;
+        bool acc_c = false, leaf = false, opn = false, nr = false, sep = false;
         uint32_t first = 0, count = 0, child = 0, nch = 0;
-        vec4_t<T> pcs = make_vec4((T)0, (T)0, (T)0, (T)0);
+        double ncom[3] = {0.0, 0.0, 0.0}, nM = 0.0, rb2 = 0.0, D2 = 0.0;
         if (have) {
             const Node nd = A.node[id];
             double D1 = dist2(gap_pt(G.lo[0], G.hi[0], nd.com[0]),
                               gap_pt(G.lo[1], G.hi[1], nd.com[1]),
                               gap_pt(G.lo[2], G.hi[2], nd.com[2]));
-            double D2 = dist2(gap_box(G.lo[0], G.hi[0], nd.blo[0], nd.blo[0] + nd.l),
-                              gap_box(G.lo[1], G.hi[1], nd.blo[1], nd.blo[1] + nd.l),
-                              gap_box(G.lo[2], G.hi[2], nd.blo[2], nd.blo[2] + nd.l));
-            bool sep = HYBRID ? (D2 >= R2sq) : (D2 > 0.0);
+            D2 = dist2(gap_box(G.lo[0], G.hi[0], nd.blo[0], nd.blo[0] + nd.l),
+                       gap_box(G.lo[1], G.hi[1], nd.blo[1], nd.blo[1] + nd.l),
+                       gap_box(G.lo[2], G.hi[2], nd.blo[2], nd.blo[2] + nd.l));
+            sep = HYBRID ? (D2 >= R2sq) : (D2 > 0.0);
             nch = nd.meta & 255u;
-            acc_c = (D1 >= nd.rb2) && sep;
-            leaf = !acc_c && nch == 0;
-            opn = !acc_c && nch != 0;
-            nr = HYBRID && leaf && (D2 < R2sq);
+            rb2 = nd.rb2;
+            acc_c = (D1 >= rb2) && sep;
             first = nd.first;
             count = nd.count;
             child = nd.child;
-            if (acc_c)
-                pcs = make_vec4((T)(nd.com[0] - G.c[0]), (T)(nd.com[1] - G.c[1]),
-                                (T)(nd.com[2] - G.c[2]), (T)nd.M);
+            for (int a = 0; a < 3; a++) ncom[a] = nd.com[a];
+            nM = nd.M;
         }
+        if (MINS) {
+            // the paper's group rule: a cell is measured by its nearest sink,
+            // min_i |u_i - COM|^2, never below the box distance D1, so the box
+            // test above settles acceptances early; the others are decided
+            // here, by all lanes together (sink positions are broadcast)
+            const bool need = have && !acc_c && sep;
+            if (__ballot(need)) {
+                double Dm = INFINITY;
+                for (int k = 0; k < G.ns; k++) {
+                    const double px = uniform_lane_f64(me.x, k), py = uniform_lane_f64(me.y, k),
+                                 pz = uniform_lane_f64(me.z, k);
+                    const double dx = ncom[0] - px, dy = ncom[1] - py, dz = ncom[2] - pz;
+                    Dm = fmin(Dm, fma(dz, dz, fma(dy, dy, dx * dx)));
+                }
+                if (need) acc_c = Dm >= rb2;
+            }
+        }
+        leaf = have && !acc_c && nch == 0;
+        opn = have && !acc_c && nch != 0;
+        nr = HYBRID && leaf && (D2 < R2sq);
+        vec4_t<T> pcs = make_vec4((T)0, (T)0, (T)0, (T)0);
+        if (acc_c)
+            pcs = make_vec4((T)(ncom[0] - G.c[0]), (T)(ncom[1] - G.c[1]), (T)(ncom[2] - G.c[2]),
+                            (T)nM);
         // accepted cells -> particle-cell sources
         uint64_t m = __ballot(acc_c);
         if (acc_c) S.pc[npc + __popcll(m & lt)] = pcs;
@@ -521,7 +550,7 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS<T> &S, uint32_t grp) {
     }
 }
 
-template <bool HYBRID, bool POT, typename T>
+template <bool HYBRID, bool POT, bool MINS, typename T>
 __global__ __launch_bounds__(64) void k_soft(ForceArgs A) {
     __shared__ SoftLDS<T> S;
     const uint32_t ng = *A.ng;
@@ -530,28 +559,33 @@ __global__ __launch_bounds__(64) void k_soft(ForceArgs A) {
         const uint32_t grp = A.order ? A.order[pos] : pos;
         HT_CHECK(grp < ng);
         HT_CHECK(A.gstart[grp + 1] > A.gstart[grp] && A.gstart[grp + 1] - A.gstart[grp] <= 64);
-        soft_group<HYBRID, POT, T>(A, S, grp);
+        soft_group<HYBRID, POT, MINS, T>(A, S, grp);
     }
 }
 
-template <typename T>
+template <bool MINS, typename T>
 void launch_soft_t(const ForceArgs &A, bool hybrid, bool pot, dim3 grid, hipStream_t s) {
     dim3 block(64);
     if (hybrid) {
-        if (pot) hipLaunchKernelGGL((k_soft<true, true, T>), grid, block, 0, s, A);
-        else hipLaunchKernelGGL((k_soft<true, false, T>), grid, block, 0, s, A);
+        if (pot) hipLaunchKernelGGL((k_soft<true, true, MINS, T>), grid, block, 0, s, A);
+        else hipLaunchKernelGGL((k_soft<true, false, MINS, T>), grid, block, 0, s, A);
     } else {
-        if (pot) hipLaunchKernelGGL((k_soft<false, true, T>), grid, block, 0, s, A);
-        else hipLaunchKernelGGL((k_soft<false, false, T>), grid, block, 0, s, A);
+        if (pot) hipLaunchKernelGGL((k_soft<false, true, MINS, T>), grid, block, 0, s, A);
+        else hipLaunchKernelGGL((k_soft<false, false, MINS, T>), grid, block, 0, s, A);
     }
 }
 
-void launch_soft(const ForceArgs &A, bool hybrid, bool pot, int precision, int n_wg,
-                 hipStream_t s) {
+void launch_soft(const ForceArgs &A, bool hybrid, bool pot, int precision, bool min_sinks,
+                 int n_wg, hipStream_t s) {
     HT_CHECK(n_wg > 0 && n_wg % 8 == 0);
     const dim3 grid((unsigned)n_wg);
-    if (precision == 1) launch_soft_t<double>(A, hybrid, pot, grid, s);
-    else launch_soft_t<float>(A, hybrid, pot, grid, s);
+    if (min_sinks) {
+        if (precision == 1) launch_soft_t<true, double>(A, hybrid, pot, grid, s);
+        else launch_soft_t<true, float>(A, hybrid, pot, grid, s);
+    } else {
+        if (precision == 1) launch_soft_t<false, double>(A, hybrid, pot, grid, s);
+        else launch_soft_t<false, float>(A, hybrid, pot, grid, s);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -59,6 +59,8 @@ struct Sys {
     uint32_t pad;
     double invth2;      // 1 / theta^2 (+inf for theta = 0)
     double R2;          // hybrid cutoff, 0 in plain mode
+    double aerr;        // absolute MAC parameter a_err (0: opening radius l / theta)
+    double G;           // gravitational constant (in the absolute MAC)
 };
 
 // Per-system force parameters (device table).
@@ -181,6 +183,7 @@ struct BuildBufs {
     int32_t S;             // systems
     int32_t sysbits;       // bits of a system index (0 for S = 1)
     int32_t max_n_crit;    // largest n_crit of the systems
+    bool abs_mac;          // some system opens cells by the absolute MAC
     int64_t nchunks;       // bounding-box chunks
     // static tables
     Sys *sys;              // [S]
@@ -211,7 +214,7 @@ struct BuildBufs {
     int8_t *leaflev;       // [n] leaf level of each particle
     uint32_t *nstart;      // [n+1] nodes starting at each position, scanned
     uint32_t *scan_part;   // scan partials
-    uint32_t *nn;          // device node count
+    uint32_t *nn;          // [4] device node count in nn[0]; nn[2] work items of the b_max pass
     uint32_t *pre_key;     // [nnmax] (level, system) key of each pre-order node
     uint32_t *pre_val;     // [nnmax] pre-order index
     uint32_t *lvl_key2;    // [nnmax] partitioned keys
@@ -236,6 +239,9 @@ struct BuildBufs {
     uint32_t *hkey;        // [2n] sort keys (descending cost buckets)
     uint32_t *hval;        // [2n] group indices before the sort
     uint32_t *horder;      // [n] dispatch position -> hard group
+    double *B2;            // [nnmax] sum m |COM - u|^2 per node (absolute MAC only)
+    unsigned long long *bmax;  // [nnmax] bits of max |COM - u|^2 per node (absolute MAC only)
+    uint32_t *bitems;      // [nnmax + 1] work items of the b_max pass (absolute MAC only)
     uint32_t *hlist;       // [kListPerSink * n] recorded hard search lists (node ids)
     uint32_t *hlen;        // [n] their lengths per hard group, or kNoList
     uint32_t *sorder;      // [2n] dispatch position -> soft group (first ng entries)
@@ -293,8 +299,8 @@ struct ForceArgs {
     unsigned long long *tally;  // [kTallySlots][kTallyStride] interaction tally slots
     uint32_t *status;
 };
-void launch_soft(const ForceArgs &A, bool hybrid, bool pot, int precision, int n_wg,
-                 hipStream_t s);
+void launch_soft(const ForceArgs &A, bool hybrid, bool pot, int precision, bool min_sinks,
+                 int n_wg, hipStream_t s);
 void launch_hard(const ForceArgs &A, int n_wg, hipStream_t s);
 
 // Integrator and layout kernels (integrate.hip).

@@ -115,3 +115,26 @@ def test_hard_search_replay_emulated(orc, emu, name):
         assert np.array_equal(ngb.astype(np.int64), ongb)
         e = _rel(ah.astype(np.float64), oah)[ongb > 0]
         assert np.percentile(e, 99) <= TOL_P99
+
+
+@pytest.mark.parametrize("name,hybrid,group_mac", [
+    ("plummer4k", 1, 0), ("plummer4k", 1, 1), ("cube5000", 0, 1), ("dups_lognormal", 0, 1)])
+def test_soft_kernel_abs_mac_emulated(orc, emu, name, hybrid, group_mac):
+    """The absolute MAC (a_err = 2^-8) with either group rule: lists and
+    forces of the emulated kernels against the oracle's."""
+    x, v, m, eps, R1, R2, G = _case(name)
+    m32 = m.astype(np.float32)
+    m64 = m32.astype(np.float64)
+    aerr = 2.0 ** -8
+    t = emu.EmuTree(x, v.astype(np.float32), m32, G=G, eps=eps, R1=R1, R2=R2, hybrid=hybrid,
+                    a_err=aerr, group_mac=group_mac)
+    t.build_tree()
+    acc = t.soft_force()
+    t.sync()
+    T = orc.Tree(x, m64, n_crit=16, theta=0.5).set_mac(aerr, G, group_mac)
+    assert np.array_equal(t.group_starts().astype(np.int64), T.group_starts())
+    npc, nfar, nnear = t.group_counts()
+    opc, ofar, onear = T.walk_counts(R2, hybrid)
+    assert np.array_equal(npc, opc) and np.array_equal(nfar, ofar) and np.array_equal(nnear, onear)
+    oacc, _, _ = T.soft(G, eps, R1, R2, hybrid)
+    assert np.percentile(_rel(acc.astype(np.float64), oacc), 99) <= TOL_P99

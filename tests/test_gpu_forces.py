@@ -260,3 +260,41 @@ def test_hard_force_after_refits(orc, name, G, reuse):
         e = rel_err(ah.cpu().numpy().astype(np.float64), oah)
         report("hard after refit %d" % k, e[ongb > 0])
         assert np.percentile(e[ongb > 0], 99) <= TOL_P99
+
+
+@pytest.mark.parametrize("name,G", [("plummer4k", 1.0), ("lognormal4k", 2.5),
+                                    ("dups_lognormal", 2.5), ("cube5000", 1.0)])
+@pytest.mark.parametrize("group_mac", [0, 1])
+@pytest.mark.parametrize("hybrid", [0, 1])
+def test_abs_mac_parity(orc, name, G, group_mac, hybrid):
+    """The paper's absolute MAC (a_err = 2^-8, section II.B) with the box or
+    the minimum-over-sinks group rule: B2, b_max^2 and r_b^2 of every node bit
+    for bit (correctly rounded sqrt and division on both sides), list sizes
+    bit for bit, forces within the tolerance."""
+    torch, P = need_gpu()
+    (x, v, m), eps, R1, R2 = _wl(name)
+    x, v32, m32, v64, m64 = as_inputs(x, v, m)
+    aerr = 2.0 ** -8
+    print("abs mac", name, "G", G, "group_mac", group_mac, "hybrid", hybrid, flush=True)
+    t = make_tree(P, torch, x, v32, m32, G=G, eps=eps, R1=R1, R2=R2, hybrid=hybrid,
+                  a_err=aerr, group_mac=group_mac)
+    t.build_tree()
+    acc = t.soft_force()
+    t.sync()
+    st = t.stats()
+    T = orc.Tree(x, m64, n_crit=16, theta=0.5).set_mac(aerr, G, group_mac)
+    g, o = t.export_nodes(), T.nodes()
+    gk = np.lexsort((g["first"], g["level"]))
+    ok = np.lexsort((o["first"], o["level"]))
+    gB2, gbm, grb = (a[gk] for a in t.export_node_mac())
+    oB2, obm = (a[ok] for a in T.node_mac())
+    assert np.array_equal(gB2, oB2) and np.array_equal(gbm, obm)
+    assert np.array_equal(grb, o["rb2"][ok])
+    npc, nfar, nnear = t.group_counts()
+    opc, ofar, onear = T.walk_counts(R2, hybrid)
+    assert np.array_equal(npc, opc) and np.array_equal(nfar, ofar) and np.array_equal(nnear, onear)
+    oacc, _, ointer = T.soft(G, eps, R1, R2, hybrid)
+    assert st["soft_interactions"] == ointer
+    e = rel_err(acc.cpu().numpy().astype(np.float64), oacc)
+    report("abs mac soft acc", e)
+    assert np.percentile(e, 99) <= TOL_P99

@@ -159,3 +159,53 @@ def test_hernquist_2e23(orc, hq, theta):
     print("C3 theta %.1f: soft vs oracle p99 fp32 %.3e fp64 %.3e | force vs direct (%d sinks, "
           "unpinned): %s" % (theta, np.percentile(e32, 99), np.percentile(e64, 99), ds.size,
                              "; ".join(line)), flush=True)
+
+
+def test_plummer_2e20_abs_mac(orc):
+    """The absolute MAC (a_err = 2^-8) with the minimum-over-sinks group rule
+    at N = 2^20: B2, b_max^2 and r_b^2 of all nodes bit for bit (about 8e5
+    device square roots and divisions checked against the host's correctly
+    rounded ones), per-group list sizes and the interaction count in full,
+    forces on the 2^14 sampled sinks; the force error against the FP64
+    direct sum is reported (parity unpinned)."""
+    torch, P = need_gpu()
+    I = _inputs(synth.WORKLOADS["plummer1m"])
+    wl = I["wl"]
+    aerr = 2.0 ** -8
+    t = make_tree(P, torch, I["x"], I["v32"], I["m32"], eps=wl.eps, R1=wl.R1, R2=wl.R2,
+                  n_crit=wl.n_crit, a_err=aerr, group_mac=1)
+    t.build_tree()
+    a_s = t.soft_force()
+    a_h, _ = t.hard_force()
+    t.sync()
+    st = t.stats()
+    T = orc.Tree(I["x"], I["m64"], n_crit=wl.n_crit, theta=wl.theta).set_mac(aerr, 1.0, 1)
+    g, o = t.export_nodes(), T.nodes()
+    gk = np.lexsort((g["first"], g["level"]))
+    ok = np.lexsort((o["first"], o["level"]))
+    gB2, gbm, grb = (a[gk] for a in t.export_node_mac())
+    oB2, obm = (a[ok] for a in T.node_mac())
+    assert np.array_equal(gB2, oB2) and np.array_equal(gbm, obm)
+    assert np.array_equal(grb, o["rb2"][ok])
+    gst = T.group_starts()
+    assert np.array_equal(t.group_starts().astype(np.int64), gst)
+    npc, nfar, nnear = t.group_counts()
+    opc, ofar, onear = T.walk_counts(wl.R2, 1)
+    assert np.array_equal(npc, opc) and np.array_equal(nfar, ofar) and np.array_equal(nnear, onear)
+    inter = int((np.diff(gst) * (opc + ofar + onear)).sum())
+    assert st["soft_interactions"] == inter
+    operm, _, _ = T.sorted()
+    groups = _sample_groups(gst, operm, I["sinks"])
+    oacc, _, _ = T.soft(1.0, wl.eps, wl.R1, wl.R2, 1, groups=groups)
+    s = I["sinks"]
+    a_s = a_s.cpu().numpy().astype(np.float64)
+    e = rel_err(a_s[:, s], oacc[:, s])
+    report("abs mac soft, 2^14 sampled sinks", e)
+    assert np.percentile(e, 99) <= 1e-5
+    ds = s[:: s.size // N_DIRECT_SAMPLE][:N_DIRECT_SAMPLE]
+    ref = orc.direct(I["x"], I["m64"], 1.0, wl.eps, sinks=ds)
+    tot = a_s[:, ds] + a_h.cpu().numpy().astype(np.float64)[:, ds]
+    ed = rel_err(tot, ref)
+    print("abs mac a_err 2^-8, min over sinks: %d soft interactions; force vs direct (%d sinks, "
+          "unpinned) p50 %.3e p99 %.3e" % (inter, ds.size, np.percentile(ed, 50),
+                                           np.percentile(ed, 99)), flush=True)
