@@ -205,9 +205,9 @@ def comparator(P, torch, wl, x, v32, m32, hyb_ms_step, hard_ms_call, steps):
     ref = direct_sample(torch, X, M.double(), idx, 1.0, wl.eps)
     refn = ref.norm(dim=0)
 
-    def p99(theta, hybrid):
+    def p99(theta, hybrid, **kw):
         p = P.default_params(eps=wl.eps, theta=theta, R1=wl.R1, R2=wl.R2, hybrid=hybrid,
-                             n_crit=wl.n_crit)
+                             n_crit=wl.n_crit, **kw)
         t = P.HTree(n, p)
         t.set_state(X, V, M)
         t.build_tree()
@@ -246,6 +246,32 @@ def comparator(P, torch, wl, x, v32, m32, hyb_ms_step, hard_ms_call, steps):
     ms_tree = 1e3 * (time.perf_counter() - t0) / steps
     st = t.stats()
     t.close()
+    # the paper's own opening rule (section II.B absolute MAC, a_err = 2^-8 as
+    # in section IV.A, groups measured by their nearest sink) in the same
+    # hybrid step: its force error on the same sample and its step time
+    mac = dict(a_err=2.0 ** -8, group_mac=1)
+    e_mac = p99(wl.theta, 1, **mac)
+    p = P.default_params(eps=wl.eps, R1=wl.R1, R2=wl.R2, dt_soft=wl.dt_soft, n_sub=wl.n_sub,
+                         hybrid=1, n_crit=wl.n_crit, flags=P.F_TIMING | P.F_REUSE, **mac)
+    t = P.HTree(n, p)
+    t.set_state(X, V, M)
+    t.step(1)
+    t.sync()
+    t.stats()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        t.step(1)
+    t.sync()
+    ms_mac = 1e3 * (time.perf_counter() - t0) / steps
+    sm = t.stats()
+    t.close()
+    _log("paper MAC: p99 %.3e, %.3f ms per step" % (e_mac, ms_mac))
+    paper_mac = {"a_err": 2.0 ** -8, "group_rule": "minimum over sinks",
+                 "p99_force_error": e_mac, "ms_per_step": ms_mac,
+                 "soft_interactions_per_step": sm["soft_interactions"] / steps,
+                 "phase_ms_per_step": {"build": sm["ms_build"] / steps,
+                                       "soft": sm["ms_soft"] / steps,
+                                       "hard": sm["ms_hard"] / steps}}
     return {
         "what": "plain tree (hybrid=0, one force per dt_h=1/64) at the hybrid's force accuracy",
         "reference": "FP64 direct sum on %d sampled sinks (seed %d)" % (wl.sample, wl.sample_seed),
@@ -257,6 +283,7 @@ def comparator(P, torch, wl, x, v32, m32, hyb_ms_step, hard_ms_call, steps):
         "T_hard_over_T_tree": hard_ms_call / ms_tree,
         "paper_context": "the paper reports R_hybrid 0.8-0.9 and 0.7 and T_hard about 0.4 of a "
                          "tree force on its GPU cluster (different hardware)",
+        "hybrid_with_paper_mac": paper_mac,
     }
 
 
