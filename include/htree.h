@@ -226,14 +226,17 @@ htree_status htree_stats(htree_ctx *ctx, htree_counters *out);
  * Synchronises the stream. */
 htree_status htree_export_node_mac(htree_ctx *ctx, double *B2, double *bmax2, double *rb2);
 
-/* Sink groups of the last build (section III.A.2: sinks that share one
- * traversal).  A group holds at most group_size particles inside one tree
- * cell: a cell with at most group_size particles is a group; a bigger cell is
- * split into its children; where all its children are small, consecutive
- * children (octant order) are packed while the total stays <= group_size; a
- * bigger leaf is cut into chunks.  htree_group_count returns their number (-1
- * on error); htree_export_groups writes the count + 1 start positions (sorted
- * order, the last one n) to a host array.  Both synchronise the stream. */
+/* Soft sink groups of the last build (section III.A.2: sinks that share one
+ * traversal; these are the groups of the soft force and of its list sizes).
+ * With g = group_size and L = group_cell * g: the chunking cells are the
+ * cells of at most L particles whose parent holds more (the root if it holds
+ * at most L) and the leaves whose parent holds more; each chunking cell is
+ * cut into consecutive chunks of g particles in sorted order (the last one
+ * shorter), and every chunk is a group.  htree_group_count returns their
+ * number (-1 on error); htree_export_groups writes the count + 1 start
+ * positions (sorted order, the last one n) to a host array.  Both
+ * synchronise the stream.  (The hard force groups its sinks by a rule of its
+ * own, which does not change any result.) */
 int64_t htree_group_count(htree_ctx *ctx);
 htree_status htree_export_groups(htree_ctx *ctx, int32_t *starts);
 
