@@ -61,13 +61,17 @@ PEAK_FP64 = 78.6
 PEAK_FP32 = 78.6
 PEAK_FP32_PACKED = 157.3
 
-# HBM bytes per launch of the soft kernel at this workload, from rocprofv3
-# FETCH_SIZE and WRITE_SIZE runs scaled by a plain-copy calibration (the
-# summary with commands is profiles/counters_plummer1m_step.txt).  Valid only
+# HBM bytes per launch at this workload, from rocprofv3 counters: reads from
+# the L2-to-memory read requests counted by size (32, 64, 128 bytes: exact;
+# FETCH_SIZE counts a 128-byte request as 64 bytes on this GPU, which a plain
+# copy and a random gather calibrate), writes from WRITE_SIZE (exact on a plain
+# copy).  The hard figure is the mean of a step's four launches (one after the
+# build that records the searches, three after refits that replay them).  The
+# summary with commands is profiles/counters_plummer1m_step.txt.  Valid only
 # for the kernel source it was measured on: reported as null once force.hip or
 # htree_dev.h differ from that source.
-SOFT_TRAFFIC = {"bytes": 1805.9e6, "source_hash": "9338695e88294fb1"}
-HARD_TRAFFIC = {"bytes": 1954.7e6, "source_hash": "9338695e88294fb1"}
+SOFT_TRAFFIC = {"bytes": 1787.8e6, "source_hash": "3e3d89c0b8a62656"}
+HARD_TRAFFIC = {"bytes": 2187.6e6, "source_hash": "3e3d89c0b8a62656"}
 
 
 def _kernel_source_hash():
@@ -465,8 +469,9 @@ def main():
     ap.add_argument("--ensemble-steps", type=int, default=8)
     ap.add_argument("--serve-requests", type=int, default=20000)
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain 512 MiB device copy five times (the reference "
-                         "kernel for scaling HBM byte counters) and exit")
+                    help="only run the reference kernels for scaling HBM byte counters and "
+                         "exit: a plain 512 MiB device copy and a gather of 2^24 records of "
+                         "32 bytes in random order, five times each")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
@@ -475,8 +480,23 @@ def main():
         for _ in range(5):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4,
-                          "launches": 5}))
+        del a, b
+        # the force kernels gather records of particles (x, y, z, m: 32 bytes)
+        # by index, so the counters are also calibrated on a gather of 32-byte
+        # rows in random order
+        g = torch.Generator(device="cuda")
+        g.manual_seed(7)
+        rows = 1 << 24
+        src = torch.ones(rows, 4, dtype=torch.float64, device="cuda")
+        idx = torch.randperm(rows, device="cuda", generator=g)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            torch.index_select(src, 0, idx, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": (1 << 27) * 4, "copy_bytes_written": (1 << 27) * 4,
+                          "gather_rows": rows, "gather_row_bytes": 32,
+                          "gather_bytes_read": rows * 32 + rows * 8,
+                          "gather_bytes_written": rows * 32, "launches": 5}))
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the force path is single-GPU by design "
