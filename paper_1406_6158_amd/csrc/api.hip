@@ -236,7 +236,7 @@ void carve(Carver &C, htree_ctx *c) {
     B.bmax = C.take<unsigned long long>(B.abs_mac ? nnmax : 1);
     B.bitems = C.take<uint32_t>(B.abs_mac ? nnmax + 1 : 1);
     B.S3 = C.take<double>(3 * nnmax);
-    B.aabb = C.take<double>(6 * nnmax);
+    B.aabb = C.take<double>(8 * nnmax);
     {
         int64_t m1, m2, m3;
         refit_sizes(n, &m1, &m2, &m3);

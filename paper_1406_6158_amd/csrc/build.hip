@@ -702,6 +702,14 @@ __global__ __launch_bounds__(256) void k_level_starts(const uint32_t *lkey, int 
         for (uint32_t m = l + 1; m <= (uint32_t)kMaxLevel + 1; m++) lstart[m] = nn;
 }
 
+// Node box record b: 8 doubles (lo x, y, z, unused, hi x, y, z, unused), one
+// 64-byte line half, so a walk reads a node's box with two 32-byte loads.
+__device__ inline void store_box(double *aabb, uint32_t b, const double *lo, const double *hi) {
+    double4 *r = (double4 *)aabb + 2 * (int64_t)b;
+    r[0] = make_double4(lo[0], lo[1], lo[2], 0.0);
+    r[1] = make_double4(hi[0], hi[1], hi[2], 0.0);
+}
+
 // |p - q|^2 as fma(dz, dz, fma(dy, dy, dx * dx)) with d = p - q.
 __device__ inline double sqdist(const double *p, double qx, double qy, double qz) {
     const double dx = p[0] - qx, dy = p[1] - qy, dz = p[2] - qz;
@@ -748,8 +756,8 @@ __global__ __launch_bounds__(256) void k_level_pass(Node *node, const double4 *s
             for (uint32_t k = 0; k < nch; k++) {
                 const uint32_t c = N.child + k;
                 for (int a = 0; a < 3; a++) {
-                    lo[a] = fmin(lo[a], aabb[a * nnmax + c]);
-                    hi[a] = fmax(hi[a], aabb[(3 + a) * nnmax + c]);
+                    lo[a] = fmin(lo[a], aabb[8 * (int64_t)c + a]);
+                    hi[a] = fmax(hi[a], aabb[8 * (int64_t)c + 4 + a]);
                 }
                 if (MOM) {
                     M += node[c].M;
@@ -757,10 +765,7 @@ __global__ __launch_bounds__(256) void k_level_pass(Node *node, const double4 *s
                 }
             }
         }
-        for (int a = 0; a < 3; a++) {
-            aabb[a * nnmax + b] = lo[a];
-            aabb[(3 + a) * nnmax + b] = hi[a];
-        }
+        store_box(aabb, b, lo, hi);
         if (MOM) {
             N.M = M;
             for (int a = 0; a < 3; a++) {
@@ -982,10 +987,7 @@ __global__ __launch_bounds__(256) void k_refit(const Node *node, const uint32_t 
             }
         }
     }
-    for (int a = 0; a < 3; a++) {
-        aabb[a * nnmax + b] = lo[a];
-        aabb[(3 + a) * nnmax + b] = hi[a];
-    }
+    store_box(aabb, b, lo, hi);
 }
 
 // Sizes of the three chunk levels for n particles (entries of 6 doubles).

@@ -858,11 +858,11 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
         bool leaf = false, opn = false, keep = false;
         uint32_t first = 0, count = 0, child = 0, nch = 0;
         if (have) {
-            const double *bx = A.aabb + id;
-            const int64_t nm = A.nnmax;
-            double D2 = dist2(gap_box(blo[0], bhi[0], bx[0], bx[3 * nm]),
-                              gap_box(blo[1], bhi[1], bx[nm], bx[4 * nm]),
-                              gap_box(blo[2], bhi[2], bx[2 * nm], bx[5 * nm]));
+            const double4 *bx = (const double4 *)A.aabb + 2 * (int64_t)id;
+            const double4 bl = bx[0], bh = bx[1];
+            double D2 = dist2(gap_box(blo[0], bhi[0], bl.x, bh.x),
+                              gap_box(blo[1], bhi[1], bl.y, bh.y),
+                              gap_box(blo[2], bhi[2], bl.z, bh.z));
             const Node &nd = A.node[id];
             nch = nd.meta & 255u;
             leaf = D2 < pad2 && nch == 0;

@@ -225,7 +225,7 @@ struct BuildBufs {
     uint32_t *ptmp_k, *ptmp_v;  // [nnmax] partition scratch
     Node *node;            // [nnmax] level order
     double *S3;            // [3][nnmax] first mass moments
-    double *aabb;          // [6][nnmax] node boxes in master coordinates (lo xyz, hi xyz)
+    double *aabb;          // [nnmax][8] node boxes in master coordinates: lo x, y, z, -, hi x, y, z, -
     double *cbox;          // boxes of aligned 32, 32^2, 32^3-particle chunks (refit)
     uint32_t *lstart;      // [kMaxLevel + 2] first node of each level
     int64_t nnmax;
@@ -282,7 +282,7 @@ struct ForceArgs {
     const double4 *src;       // sorted build-frame positions and masses
     const double *x;          // [3][n] sorted FP64 positions (hard test)
     const float *m;           // [n] sorted masses
-    const double *aabb;       // [6][nnmax] node boxes, master coordinates
+    const double *aabb;       // [nnmax][8] node boxes, master coordinates (lo xyz, -, hi xyz, -)
     int64_t nnmax;
     const Frame *frame;       // [S]
     const uint32_t *order;    // null, or dispatch position -> group (a permutation)
