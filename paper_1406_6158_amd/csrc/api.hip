@@ -237,6 +237,7 @@ void carve(Carver &C, htree_ctx *c) {
     B.bitems = C.take<uint32_t>(B.abs_mac ? nnmax + 1 : 1);
     B.S3 = C.take<double>(3 * nnmax);
     B.aabb = C.take<double>(8 * nnmax);
+    B.xm = C.take<double4>(n);
     {
         int64_t m1, m2, m3;
         refit_sizes(n, &m1, &m2, &m3);
@@ -345,9 +346,8 @@ ForceArgs force_args(htree_ctx *c) {
     A.sys_of = B.sys_of;
     A.sysf = B.sysf;
     A.src = B.src;
-    A.x = B.x[B.cur];
-    A.m = B.m[B.cur];
     A.aabb = B.aabb;
+    A.xm = B.xm;
     A.nnmax = B.nnmax;
     A.frame = B.frame;
     A.order = nullptr;
@@ -471,7 +471,7 @@ htree_status do_hard(htree_ctx *c) {
 htree_status kick(htree_ctx *c, double ks, double kh, double dt_drift) {
     BuildBufs &B = c->B;
     const int k = B.cur;
-    launch_kick_drift(B.x[k], B.v[k], ks != 0.0 ? B.as[k] : nullptr, (float)ks,
+    launch_kick_drift(B.x[k], B.xm, B.m[k], B.v[k], ks != 0.0 ? B.as[k] : nullptr, (float)ks,
                       kh != 0.0 ? B.ah[k] : nullptr, (float)kh, dt_drift, c->n, c->stream);
     HIP_OK(hipGetLastError());
     if (dt_drift != 0.0) c->tree = c->moments = c->boxes = c->forces_current = false;
@@ -706,14 +706,14 @@ htree_status htree_kick_drift(htree_ctx *c, double dt_kick, const float *d_acc, 
     const int k = B.cur;
     if (d_acc) {
         launch_gather3(d_acc, B.perm[k], c->tmp3, c->n, c->stream);
-        launch_kick_drift(B.x[k], B.v[k], c->tmp3, (float)dt_kick, nullptr, 0.f, dt_drift, c->n,
-                          c->stream);
+        launch_kick_drift(B.x[k], B.xm, B.m[k], B.v[k], c->tmp3, (float)dt_kick, nullptr, 0.f,
+                          dt_drift, c->n, c->stream);
     } else {
         if (!c->have_soft && !c->have_hard)
             return fail(HTREE_ESTATE, "no kept accelerations to kick with");
-        launch_kick_drift(B.x[k], B.v[k], c->have_soft ? B.as[k] : nullptr, (float)dt_kick,
-                          c->have_hard ? B.ah[k] : nullptr, (float)dt_kick, dt_drift, c->n,
-                          c->stream);
+        launch_kick_drift(B.x[k], B.xm, B.m[k], B.v[k], c->have_soft ? B.as[k] : nullptr,
+                          (float)dt_kick, c->have_hard ? B.ah[k] : nullptr, (float)dt_kick,
+                          dt_drift, c->n, c->stream);
     }
     HIP_OK(hipGetLastError());
     if (dt_drift != 0.0) c->tree = c->moments = c->boxes = c->forces_current = false;

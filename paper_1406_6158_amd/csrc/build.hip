@@ -510,7 +510,7 @@ __global__ __launch_bounds__(256) void k_gather(
     const uint32_t *idx, int64_t n, const uint32_t *sys_of, const Frame *frames, const double *x0,
     const float *v0, const float *m0, const uint32_t *p0, const float *as0, const float *ah0,
     const uint32_t *wc0, const uint32_t *wh0, double *x1, float *v1, float *m1, uint32_t *p1,
-    float *as1, float *ah1, uint32_t *wc1, uint32_t *wh1, double4 *src) {
+    float *as1, float *ah1, uint32_t *wc1, uint32_t *wh1, double4 *src, double4 *xm) {
     int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (p >= n) return;
     uint32_t o = idx[p];
@@ -531,6 +531,7 @@ __global__ __launch_bounds__(256) void k_gather(
     wc1[p] = wc0[o];
     wh1[p] = wh0[o];
     src[p] = make_double4(xx[0] - F.lo[0], xx[1] - F.lo[1], xx[2] - F.lo[2], (double)mm);
+    xm[p] = make_double4(xx[0], xx[1], xx[2], (double)mm);
 }
 
 // Permutes the state into the new key order.  The kept accelerations follow
@@ -543,12 +544,12 @@ void launch_gather(BuildBufs &B, bool keep_acc, hipStream_t s) {
         hipLaunchKernelGGL(k_gather<true>, grid, dim3(256), 0, s, B.idx[0], n, B.sys_of, B.frame,
                            B.x[c], B.v[c], B.m[c], B.perm[c], B.as[c], B.ah[c], B.wsoft[c],
                            B.whard[c], B.x[d], B.v[d], B.m[d], B.perm[d], B.as[d], B.ah[d],
-                           B.wsoft[d], B.whard[d], B.src);
+                           B.wsoft[d], B.whard[d], B.src, B.xm);
     else
         hipLaunchKernelGGL(k_gather<false>, grid, dim3(256), 0, s, B.idx[0], n, B.sys_of,
                            B.frame, B.x[c], B.v[c], B.m[c], B.perm[c], B.as[c], B.ah[c],
                            B.wsoft[c], B.whard[c], B.x[d], B.v[d], B.m[d], B.perm[d], B.as[d],
-                           B.ah[d], B.wsoft[d], B.whard[d], B.src);
+                           B.ah[d], B.wsoft[d], B.whard[d], B.src, B.xm);
     B.cur = d;
 }
 

@@ -688,7 +688,8 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
     const SysF P = A.sysf[sys];
     const int64_t n = A.n;
     const uint32_t mi = act ? b0 + lane : b0;
-    const double xi = A.x[mi], yi = A.x[n + mi], zi = A.x[2 * n + mi];
+    const double4 me = A.xm[mi];
+    const double xi = me.x, yi = me.y, zi = me.z;
     // box of the sinks' master positions (wave-uniform); the node boxes are
     // in master coordinates too
     double blo[3], bhi[3];
@@ -794,10 +795,11 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
         g_pi = take_items(S.efirst, S.ecnt, nr, want, S.scan, order);
         g_want = want;
         if (lane < want) {
-            gx = A.x[g_pi];
-            gy = A.x[n + g_pi];
-            gz = A.x[2 * n + g_pi];
-            gm = A.m[g_pi];
+            const double4 q = A.xm[g_pi];
+            gx = q.x;
+            gy = q.y;
+            gz = q.z;
+            gm = (float)q.w;
         }
         tot -= (uint32_t)want;
     };

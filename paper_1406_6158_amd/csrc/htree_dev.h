@@ -225,6 +225,9 @@ struct BuildBufs {
     uint32_t *ptmp_k, *ptmp_v;  // [nnmax] partition scratch
     Node *node;            // [nnmax] level order
     double *S3;            // [3][nnmax] first mass moments
+    double4 *xm;           // [n] key-order master positions and masses (x, y, z, m) in one
+                           // record per particle, for the hard kernel's gathers; written by
+                           // the gather of each build and by every drift
     double *aabb;          // [nnmax][8] node boxes in master coordinates: lo x, y, z, -, hi x, y, z, -
     double *cbox;          // boxes of aligned 32, 32^2, 32^3-particle chunks (refit)
     uint32_t *lstart;      // [kMaxLevel + 2] first node of each level
@@ -280,8 +283,7 @@ struct ForceArgs {
     const uint32_t *sys_of;   // [n]
     const SysF *sysf;         // [S]
     const double4 *src;       // sorted build-frame positions and masses
-    const double *x;          // [3][n] sorted FP64 positions (hard test)
-    const float *m;           // [n] sorted masses
+    const double4 *xm;        // [n] key-order master positions and masses (hard kernel)
     const double *aabb;       // [nnmax][8] node boxes, master coordinates (lo xyz, -, hi xyz, -)
     int64_t nnmax;
     const Frame *frame;       // [S]
@@ -304,8 +306,8 @@ void launch_soft(const ForceArgs &A, bool hybrid, bool pot, int precision, bool 
 void launch_hard(const ForceArgs &A, int n_wg, hipStream_t s);
 
 // Integrator and layout kernels (integrate.hip).
-void launch_kick_drift(double *x, float *v, const float *a1, float c1, const float *a2, float c2,
-                       double dt_drift, int64_t n, hipStream_t s);
+void launch_kick_drift(double *x, double4 *xm, const float *m, float *v, const float *a1, float c1,
+                       const float *a2, float c2, double dt_drift, int64_t n, hipStream_t s);
 void launch_scatter3(const float *src_sorted, const uint32_t *perm, float *dst, int64_t n,
                      hipStream_t s);
 void launch_scatter1f(const float *src_sorted, const uint32_t *perm, float *dst, int64_t n,

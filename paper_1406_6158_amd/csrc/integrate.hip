@@ -10,24 +10,32 @@ constexpr int kNT = 256;
 static inline dim3 grid_for(int64_t n) { return dim3((unsigned)((n + kNT - 1) / kNT)); }
 
 // v += c1 a1 + c2 a2 (FP32; either term may be absent), then x += dt v (FP64).
-__global__ __launch_bounds__(kNT) void k_kick_drift(double *x, float *v, const float *a1, float c1,
+// v += c1 a1 + c2 a2 (FP32), then x += dt v (FP64); the packed copy xm of
+// the positions (with the masses m) follows the drift.
+__global__ __launch_bounds__(kNT) void k_kick_drift(double *x, double4 *xm, const float *m,
+                                                    float *v, const float *a1, float c1,
                                                     const float *a2, float c2, double dt,
                                                     int64_t n) {
     int64_t i = (int64_t)blockIdx.x * kNT + threadIdx.x;
     if (i >= n) return;
+    double xn[3];
     for (int a = 0; a < 3; a++) {
         float vv = v[a * n + i];
         if (a1) vv = vv + c1 * a1[a * n + i];
         if (a2) vv = vv + c2 * a2[a * n + i];
         v[a * n + i] = vv;
-        if (dt != 0.0) x[a * n + i] = x[a * n + i] + dt * (double)vv;
+        if (dt != 0.0) {
+            xn[a] = x[a * n + i] + dt * (double)vv;
+            x[a * n + i] = xn[a];
+        }
     }
+    if (dt != 0.0 && xm) xm[i] = make_double4(xn[0], xn[1], xn[2], (double)m[i]);
 }
 
-void launch_kick_drift(double *x, float *v, const float *a1, float c1, const float *a2, float c2,
-                       double dt_drift, int64_t n, hipStream_t s) {
-    hipLaunchKernelGGL(k_kick_drift, grid_for(n), dim3(kNT), 0, s, x, v, a1, c1, a2, c2, dt_drift,
-                       n);
+void launch_kick_drift(double *x, double4 *xm, const float *m, float *v, const float *a1, float c1,
+                       const float *a2, float c2, double dt_drift, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_kick_drift, grid_for(n), dim3(kNT), 0, s, x, xm, m, v, a1, c1, a2, c2,
+                       dt_drift, n);
 }
 
 __global__ __launch_bounds__(kNT) void k_scatter3(const float *src, const uint32_t *perm,
