@@ -137,6 +137,15 @@ __device__ inline double uniform_lane_f64(double v, int k) {
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
+// Capacity guard of the walks' LDS queues (wave-uniform `over`).  The
+// bounds are kept by construction, so this never fires; if it did, the
+// context's status word would report HTREE_EOVERFLOW (htree_sync) and the
+// caller drops the group's remaining work instead of writing past a queue.
+__device__ inline bool over_capacity(uint32_t *status, bool over) {
+    if (over && __lane_id() == 0) atomicOr(status, kStatusOverflow);
+    return over;
+}
+
 // A wave-uniform double held in scalar registers.
 __device__ inline double uniform_f64(double v) {
     const uint64_t b = (uint64_t)__double_as_longlong(v);
@@ -418,13 +427,18 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS<T> &S, uint32_t grp) {
         if (acc_c)
             pcs = make_vec4((T)(ncom[0] - G.c[0]), (T)(ncom[1] - G.c[1]), (T)(ncom[2] - G.c[2]),
                             (T)nM);
+        const bool fr = leaf && !nr;
+        if (over_capacity(A.status, npc + __popcll(__ballot(acc_c)) > kPC ||
+                                        nfr + __popcll(__ballot(fr)) > kRQ ||
+                                        nnr + __popcll(__ballot(nr)) > kRQ ||
+                                        top + __popcll(__ballot(opn)) > kStk))
+            break;
         // accepted cells -> particle-cell sources
         uint64_t m = __ballot(acc_c);
         if (acc_c) S.pc[npc + __popcll(m & lt)] = pcs;
         npc += __popcll(m);
         n_pc += __popcll(m);
         // rejected leaves -> far / near particle ranges
-        const bool fr = leaf && !nr;
         m = __ballot(fr);
         if (fr) {
             int o = nfr + __popcll(m & lt);
@@ -856,6 +870,8 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
             if (lane < want) id = A.hlist[lbase + epos + (uint32_t)lane];
             epos += (uint32_t)want;
         }
+        // each node taken adds at most one entry (a pushed range or a leaf)
+        if (over_capacity(A.status, top + nl + want > kHardEnt)) break;
         const bool have = lane < want;
         bool leaf = false, opn = false, keep = false;
         uint32_t first = 0, count = 0, child = 0, nch = 0;
