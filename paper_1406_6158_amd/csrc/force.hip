@@ -2,12 +2,15 @@
 //
 // Soft force (section II.B walk, grouped sinks of section III.A.2, split of
 // section II.C).  One wavefront serves one sink group (at most 64 sinks,
-// consecutive in key order inside one cell), one sink per lane.  The walk is wide depth-first over a
-// stack of child ranges (first node, count) in LDS: each step takes up to 64
-// nodes from the top ranges, one per lane, and tests them in FP64 against the
-// group's bounding box:
+// consecutive in key order inside one cell), one sink per lane.  The walk is
+// wide depth-first over a stack of child ranges (first node, count) in LDS:
+// each step takes up to 64 nodes from the top ranges, one per lane, and tests
+// them in FP64 against the group's bounding box:
 //   D1 = dist^2(box_g, COM),  D2 = dist^2(box_g, cell box)
-//   accepted iff D1 >= r_b^2 and (hybrid ? D2 >= R2^2 : D2 > 0).
+//   accepted iff D1 >= r_b^2 and (hybrid ? D2 >= R2^2 : D2 > 0),
+// with r_b = l / theta or the absolute MAC of section II.B (computed by the
+// build); with the paper's group rule (MINS) a cell the box test would open is
+// measured again by its nearest sink, min_i |u_i - COM|^2, instead of D1.
 // Accepted cells become particle-cell sources, rejected leaves particle
 // sources ("near", weighted by 1 - K, iff hybrid and D2 < R2^2), other nodes
 // push the range of their (contiguous) children.  Sources are staged in LDS as
@@ -35,7 +38,9 @@
 // by the exact FP64 test fma(dz,dz, fma(dy,dy, dx*dx)) < R2^2 on the master
 // positions, and accepted pairs add K(r) times the softened pair force, in
 // FP64.  The hard kernel has its own group table (cells of at most 64
-// particles).
+// particles) and gathers one packed record (x, y, z, m) per particle.  With
+// search reuse, the first launch after a build records each group's walk and
+// the launches after refits replay it (hard_group<MODE>).
 #include "htree_dev.h"
 
 #include <math.h>
