@@ -246,9 +246,15 @@ __device__ inline void eval_far(const vec4_t<T> *t, int cnt, T sx, T sy, T sz, T
     if (POT) kahan(A.p, A.pc, ph);
 }
 
+// Near sources (leaves within R2 of the group box): the weight 1 - K(r).
+// Most of their pairs lie beyond R2, where 1 - K is exactly 1 (Y clamps to
+// 0, so w = 1 and the polynomial gives 1); u2skip is R2^2 raised by a margin
+// above the rounding of the square root, so a source for which every lane
+// has u^2 >= u2skip is summed without the weight (and without its square
+// root) and every result is the same as with it.
 template <bool POT, typename T>
 __device__ inline void eval_near(const vec4_t<T> *t, int cnt, T sx, T sy, T sz, T eps2, T R2,
-                                 T invdR, Acc<T> &A) {
+                                 T invdR, T u2skip, Acc<T> &A) {
     T ax = 0, ay = 0, az = 0, ph = 0;
 #pragma unroll 4
     for (int j = 0; j < cnt; j++) {
@@ -257,8 +263,8 @@ __device__ inline void eval_near(const vec4_t<T> *t, int cnt, T sx, T sy, T sz, 
         T u2 = fma_t(dz, dz, fma_t(dy, dy, dx * dx));
         T ri = rsqrt_t(u2 + eps2);
         T mr = q.w * ri;
-        T w = one_minus_K(sqrt_t(u2), R2, invdR);
-        T f = mr * (ri * ri) * w;
+        T f = mr * (ri * ri);
+        if (__ballot(u2 < u2skip)) f = f * one_minus_K(sqrt_t(u2), R2, invdR);
         ax = fma_t(f, dx, ax);
         ay = fma_t(f, dy, ay);
         az = fma_t(f, dz, az);
@@ -370,6 +376,7 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS<T> &S, uint32_t grp) {
     const T sz = (T)(me.z - G.c[2]);
     const double R2sq = P.R2sq;
     const T eps2 = Q.eps2;
+    const T u2skip = Q.R2 * Q.R2 * (T)(1.0 + 0x1p-18);
 
     Acc<T> acc = {{0, 0, 0}, {0, 0, 0}, 0, 0};
     uint32_t n_pc = 0, n_far = 0, n_near = 0;
@@ -514,7 +521,8 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS<T> &S, uint32_t grp) {
                     q = A.src[take_items(S.nfirst, S.ncnt, nnr, 64, S.scan)];
                     ntot -= 64;
                 }
-                eval_near<POT, T>(S.tile[buf], 64, sx, sy, sz, eps2, Q.R2, Q.invdR, acc);
+                eval_near<POT, T>(S.tile[buf], 64, sx, sy, sz, eps2, Q.R2, Q.invdR, u2skip,
+                                  acc);
                 if (!more) break;
                 buf ^= 1;
             }
@@ -536,7 +544,7 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS<T> &S, uint32_t grp) {
         uint32_t pi = take_items(S.nfirst, S.ncnt, nnr, want, S.scan);
         if (lane < want) S.tile[0][lane] = rel_src<T>(A.src[pi], G);
         __syncthreads();
-        eval_near<POT, T>(S.tile[0], want, sx, sy, sz, eps2, Q.R2, Q.invdR, acc);
+        eval_near<POT, T>(S.tile[0], want, sx, sy, sz, eps2, Q.R2, Q.invdR, u2skip, acc);
         __syncthreads();
     }
 
