@@ -134,7 +134,7 @@ htree_status htree_create(htree_ctx **ctx, const htree_params *p, int64_t n,
  * one per device, held from its first use until the process ends.  No device
  * memory is allocated by this call or by any later call on the context; the
  * caller still passes every input and output buffer.  The limit: n must need
- * at most that many workspace bytes (htree_workspace_bytes; about 750 bytes
+ * at most that many workspace bytes (htree_workspace_bytes; about 920 bytes
  * per particle with n_crit = 16, so n <= 2^16 fits), else ENOMEM.  One context
  * per device may hold the array at a time: ESTATE while another is alive.
  * htree_destroy of such a context first waits for its stream, so the next

@@ -253,23 +253,36 @@ __device__ inline void eval_far(const vec4_t<T> *t, int cnt, T sx, T sy, T sz, T
 // has u^2 >= u2skip is summed without the weight (and without its square
 // root) and every result is the same as with it.
 template <bool POT, typename T>
+__device__ inline void near_pair(const vec4_t<T> &q, T sx, T sy, T sz, T eps2, T R2, T invdR,
+                                 T u2skip, T &ax, T &ay, T &az, T &ph) {
+    T dx = q.x - sx, dy = q.y - sy, dz = q.z - sz;
+    T u2 = fma_t(dz, dz, fma_t(dy, dy, dx * dx));
+    T ri = rsqrt_t(u2 + eps2);
+    T mr = q.w * ri;
+    T f = mr * (ri * ri);
+    if (__ballot(u2 < u2skip)) f = f * one_minus_K(sqrt_t(u2), R2, invdR);
+    ax = fma_t(f, dx, ax);
+    ay = fma_t(f, dy, ay);
+    az = fma_t(f, dz, az);
+    if (POT) ph -= mr;
+}
+
+template <bool POT, typename T>
 __device__ inline void eval_near(const vec4_t<T> *t, int cnt, T sx, T sy, T sz, T eps2, T R2,
                                  T invdR, T u2skip, Acc<T> &A) {
     T ax = 0, ay = 0, az = 0, ph = 0;
-#pragma unroll 4
-    for (int j = 0; j < cnt; j++) {
-        const vec4_t<T> q = t[j];
-        T dx = q.x - sx, dy = q.y - sy, dz = q.z - sz;
-        T u2 = fma_t(dz, dz, fma_t(dy, dy, dx * dx));
-        T ri = rsqrt_t(u2 + eps2);
-        T mr = q.w * ri;
-        T f = mr * (ri * ri);
-        if (__ballot(u2 < u2skip)) f = f * one_minus_K(sqrt_t(u2), R2, invdR);
-        ax = fma_t(f, dx, ax);
-        ay = fma_t(f, dy, ay);
-        az = fma_t(f, dz, az);
-        if (POT) ph -= mr;
+    int j = 0;
+    // four sources loaded ahead of their (branching) evaluation
+    for (; j + 4 <= cnt; j += 4) {
+        vec4_t<T> q[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) q[r] = t[j + r];
+#pragma unroll
+        for (int r = 0; r < 4; r++)
+            near_pair<POT, T>(q[r], sx, sy, sz, eps2, R2, invdR, u2skip, ax, ay, az, ph);
     }
+    for (; j < cnt; j++)
+        near_pair<POT, T>(t[j], sx, sy, sz, eps2, R2, invdR, u2skip, ax, ay, az, ph);
     kahan(A.a[0], A.c[0], ax);
     kahan(A.a[1], A.c[1], ay);
     kahan(A.a[2], A.c[2], az);
