@@ -272,13 +272,13 @@ __device__ inline void eval_near(const vec4_t<T> *t, int cnt, T sx, T sy, T sz, 
                                  T invdR, T u2skip, Acc<T> &A) {
     T ax = 0, ay = 0, az = 0, ph = 0;
     int j = 0;
-    // four sources loaded ahead of their (branching) evaluation
-    for (; j + 4 <= cnt; j += 4) {
-        vec4_t<T> q[4];
+    // eight sources loaded ahead of their (branching) evaluation
+    for (; j + 8 <= cnt; j += 8) {
+        vec4_t<T> q[8];
 #pragma unroll
-        for (int r = 0; r < 4; r++) q[r] = t[j + r];
+        for (int r = 0; r < 8; r++) q[r] = t[j + r];
 #pragma unroll
-        for (int r = 0; r < 4; r++)
+        for (int r = 0; r < 8; r++)
             near_pair<POT, T>(q[r], sx, sy, sz, eps2, R2, invdR, u2skip, ax, ay, az, ph);
     }
     for (; j < cnt; j++)
