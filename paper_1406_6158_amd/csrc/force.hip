@@ -16,7 +16,9 @@
 // push the range of their (contiguous) children.  Sources are staged in LDS as
 // offsets from the group centre plus mass; every 64 of them all lanes run the
 // interaction loop, per tile in FP32 (precision 0) or FP64 (precision 1),
-// tiles merged with compensated (Kahan) summation.  No list leaves the chip.
+// tiles merged with compensated (Kahan) summation; a near source's weight is
+// evaluated only when some lane has it within R2 (beyond, it is exactly 1).
+// No list leaves the chip.
 //
 // The stack stays bounded: every popped node pushes at most one range, so a
 // step may take `want` nodes only while top + want leaves a reserve of 22
