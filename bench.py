@@ -160,8 +160,25 @@ def cpu_baseline(wl, x, m64, gpu=None, seconds_hint=20.0):
                     break
     except OSError:
         pass
+    # the same soft interaction loops on the host's SIMD units and threads
+    # (paper_1406_6158_amd/cpu: the CPU/GPU comparison of section IV.C), on
+    # synthetic groups with this tree's mean list lengths per group
+    host = None
+    try:
+        from paper_1406_6158_amd import cpu_compare
+        pc, far, near = T.walk_counts(wl.R2, 1)
+        nf = int(round(float(np.mean(pc + far))))
+        nn = int(round(float(np.mean(near))))
+        hrate, hthreads = cpu_compare.rate(nf, nn, wl.eps * wl.eps, wl.R2, 1.0 / (wl.R2 - wl.R1),
+                                           groups=2048, threads=oracle.threads(), repeat=3)
+        host = {"value": hrate, "unit": "interactions/s", "threads": hthreads,
+                "kind": "host SIMD soft interaction loops (AVX2 FP32, compensated tiles)",
+                "lists": "2048 synthetic groups of 64 sinks with this tree's mean lists per "
+                         "group: %d far (cells + far particles) and %d near sources" % (nf, nn)}
+    except (RuntimeError, OSError) as e:
+        host = {"value": None, "error": str(e)}
     return {"value": inter / dt, "unit": "interactions/s", "cores": oracle.threads(),
-            "kind": "oracle", "cpu_model": cpu,
+            "kind": "oracle", "cpu_model": cpu, "host_simd_kernels": host,
             "sample": "FP64 oracle soft force (walk + interactions) for %d of %d sink groups "
                       "of the N=2^20 Plummer tree (%d interactions, %.1f s; tree build %.1f s "
                       "not included)" % (k2, ng, inter, dt, t_build),
@@ -639,6 +656,9 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: cpu baseline (oracle) ...", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(wl, x, m32.astype(np.float64), gpu=gpu_forces)
+        hk = line["cpu_baseline"].get("host_simd_kernels") or {}
+        if hk.get("value"):
+            hk["gpu_soft_kernel_over_host"] = line["soft_kernel_interactions_per_s"] / hk["value"]
         par = line["cpu_baseline"]["parity"]
         line["parity"] = {k: par[k] for k in ("soft_p99", "hard_p99", "hard_ngb_exact",
                                               "tolerance_p99")}

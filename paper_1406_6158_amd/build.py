@@ -53,6 +53,28 @@ def build(verbose: bool = False) -> Path:
     return OUT
 
 
+# The host comparison library (cpu/soft_cpu.cpp: the soft interaction loops
+# on CPU threads, for the CPU/GPU comparison; never part of the GPU path),
+# for any x86-64 host with AVX2 and FMA.
+CPU_SRC = PKG / "cpu" / "soft_cpu.cpp"
+CPU_OUT = PKG / "libhtree_cpu.so"
+CXX = os.environ.get("CXX", "g++")
+
+
+def build_cpu(verbose: bool = False) -> Path:
+    tmp = CPU_OUT.with_suffix(".so.tmp%d" % os.getpid())
+    cmd = [CXX, "-O3", "-std=c++17", "-mavx2", "-mfma", "-fPIC", "-shared", "-pthread",
+           "-Wall", "-o", str(tmp), str(CPU_SRC)]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("g++ failed for %s:\n%s%s" % (CPU_SRC.name, r.stdout, r.stderr))
+    os.replace(tmp, CPU_OUT)
+    if verbose:
+        print("built", CPU_OUT)
+    return CPU_OUT
+
+
 if __name__ == "__main__":
     build(verbose=True)
+    build_cpu(verbose=True)
     sys.exit(0)
