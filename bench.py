@@ -131,7 +131,9 @@ def cpu_baseline(wl, x, m64, gpu=None, seconds_hint=20.0):
         sinks = np.concatenate([perm[st[k]:st[k + 1]] for k in groups])
 
         def rel(a, ref):
-            return np.linalg.norm(a - ref, axis=0) / np.linalg.norm(ref, axis=0)
+            # sinks without neighbours have a zero hard force; they are masked out below
+            with np.errstate(invalid="ignore", divide="ignore"):
+                return np.linalg.norm(a - ref, axis=0) / np.linalg.norm(ref, axis=0)
 
         es = rel(gpu["soft"][:, sinks], o_soft[:, sinks])
         hm = o_ngb > 0
