@@ -225,23 +225,37 @@ __device__ inline void kahan(T &s, T &c, T v) {
     s = t;
 }
 
+template <bool POT, typename T>
+__device__ inline void far_pair(const vec4_t<T> &q, T sx, T sy, T sz, T eps2, T &ax, T &ay, T &az,
+                                T &ph) {
+    T dx = q.x - sx, dy = q.y - sy, dz = q.z - sz;
+    T r2 = fma_t(dz, dz, fma_t(dy, dy, fma_t(dx, dx, eps2)));
+    T ri = rsqrt_t(r2);
+    T mr = q.w * ri;
+    T f = mr * (ri * ri);
+    ax = fma_t(f, dx, ax);
+    ay = fma_t(f, dy, ay);
+    az = fma_t(f, dz, az);
+    if (POT) ph -= mr;
+}
+
 template <bool POT, int CNT, typename T>
 __device__ inline void eval_far(const vec4_t<T> *t, int cnt, T sx, T sy, T sz, T eps2, Acc<T> &A) {
-    T ax = 0, ay = 0, az = 0, ph = 0;
+    // two accumulator sets (even and odd sources) halve the dependent chain
+    T ax = 0, ay = 0, az = 0, ph = 0, bx = 0, by = 0, bz = 0, pb = 0;
     const int nloop = CNT > 0 ? CNT : cnt;
-#pragma unroll 8
-    for (int j = 0; j < nloop; j++) {
-        const vec4_t<T> q = t[j];
-        T dx = q.x - sx, dy = q.y - sy, dz = q.z - sz;
-        T r2 = fma_t(dz, dz, fma_t(dy, dy, fma_t(dx, dx, eps2)));
-        T ri = rsqrt_t(r2);
-        T mr = q.w * ri;
-        T f = mr * (ri * ri);
-        ax = fma_t(f, dx, ax);
-        ay = fma_t(f, dy, ay);
-        az = fma_t(f, dz, az);
-        if (POT) ph -= mr;
+    int j = 0;
+#pragma unroll 4
+    for (; j + 2 <= nloop; j += 2) {
+        const vec4_t<T> q = t[j], p = t[j + 1];
+        far_pair<POT, T>(q, sx, sy, sz, eps2, ax, ay, az, ph);
+        far_pair<POT, T>(p, sx, sy, sz, eps2, bx, by, bz, pb);
     }
+    if (j < nloop) far_pair<POT, T>(t[j], sx, sy, sz, eps2, ax, ay, az, ph);
+    ax += bx;
+    ay += by;
+    az += bz;
+    ph += pb;
     kahan(A.a[0], A.c[0], ax);
     kahan(A.a[1], A.c[1], ay);
     kahan(A.a[2], A.c[2], az);
