@@ -136,14 +136,6 @@ __device__ inline uint32_t sched_group(uint32_t idx, uint32_t ng) {
     return idx - r + (r % 8) * kRun + r / 8;
 }
 
-// Lane k's value of v (k wave-uniform), in scalar registers.
-__device__ inline double uniform_lane_f64(double v, int k) {
-    const uint64_t b = (uint64_t)__double_as_longlong(v);
-    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, k);
-    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), k);
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-}
-
 // Capacity guard of the walks' LDS queues (wave-uniform `over`).  The
 // bounds are kept by construction, so this never fires; if it did, the
 // context's status word would report HTREE_EOVERFLOW (htree_sync) and the
@@ -451,11 +443,18 @@ __device__ void soft_group(const ForceArgs &A, SoftLDS<T> &S, uint32_t grp) {
             // here, by all lanes together (sink positions are broadcast)
             const bool need = have && !acc_c && sep;
             if (__ballot(need)) {
+                // the sinks' positions, read back as LDS broadcasts: the
+                // particle tiles are free during a walk step
+                static_assert(sizeof(S.tile) >= 3 * 64 * sizeof(double), "sink copy fits the tiles");
+                double *sp = reinterpret_cast<double *>(&S.tile[0][0]);
+                sp[lane] = me.x;
+                sp[64 + lane] = me.y;
+                sp[128 + lane] = me.z;
+                __syncthreads();
                 double Dm = INFINITY;
                 for (int k = 0; k < G.ns; k++) {
-                    const double px = uniform_lane_f64(me.x, k), py = uniform_lane_f64(me.y, k),
-                                 pz = uniform_lane_f64(me.z, k);
-                    const double dx = ncom[0] - px, dy = ncom[1] - py, dz = ncom[2] - pz;
+                    const double dx = ncom[0] - sp[k], dy = ncom[1] - sp[64 + k],
+                                 dz = ncom[2] - sp[128 + k];
                     Dm = fmin(Dm, fma(dz, dz, fma(dy, dy, dx * dx)));
                 }
                 if (need) acc_c = Dm >= rb2;
