@@ -818,10 +818,16 @@ __global__ __launch_bounds__(256) void k_bmax_small(const Node *node, const uint
     }
     items[b] = 0u;
     const double com[3] = {N.com[0], N.com[1], N.com[2]};
+    // eight particles loaded ahead of their use (a maximum is exact in any
+    // order): a node of 256 particles waits for 32 rounds of loads, not 256
+    const uint32_t f = N.first, e = N.first + N.count;
     double m = 0.0;
-    for (uint32_t i = N.first; i < N.first + N.count; i++) {
-        const double4 q = src[i];
-        m = fmax(m, sqdist(com, q.x, q.y, q.z));
+    for (uint32_t i0 = f; i0 < e; i0 += 8) {
+        double4 q[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) q[j] = src[i0 + j < e ? i0 + j : i0];
+#pragma unroll
+        for (int j = 0; j < 8; j++) m = fmax(m, sqdist(com, q[j].x, q[j].y, q[j].z));
     }
     bmax[b] = (unsigned long long)__double_as_longlong(m);
 }
