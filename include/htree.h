@@ -190,7 +190,10 @@ htree_status htree_kick_drift(htree_ctx *ctx, double dt_kick, const float *d_acc
  * node boxes to the drifted positions (same tree and groups), a_h = hard;
  * v += dt_h/2 a_h }; v += dt_s/2 a_s.  The hard force's neighbour sets are
  * exact either way.  Plain mode: n_sub = 1 with the full tree force.  Forces
- * at the initial positions are computed on the first call. */
+ * at the initial positions are computed on the first call.  Kicks that meet
+ * between two substeps (the closing half-kicks of one and the opening ones of
+ * the next, with the same forces) are applied as one update, so the
+ * velocities differ from separate half-kicks by FP32 rounding only. */
 htree_status htree_step(htree_ctx *ctx, int32_t n_soft_steps);
 
 /* Recomputes the node boxes of the last build at the current positions:

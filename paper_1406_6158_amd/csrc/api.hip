@@ -732,30 +732,40 @@ htree_status htree_step(htree_ctx *c, int32_t n_soft) {
     htree_status st = ensure_forces(c);
     if (st) return st;
     const double dts = c->p.dt_soft;
+    // The closing half-kicks of a (sub)step and the opening half-kicks of the
+    // next use the same forces, so they are applied together, with the next
+    // drift, in one launch; the closing kicks of the call's last substep are
+    // applied at its end.
+    double pend_s = 0.0, pend_h = 0.0;
     for (int32_t s = 0; s < n_soft; s++) {
         if (!c->p.hybrid) {
-            if ((st = kick(c, 0.5 * dts, 0.0, dts))) return st;
+            if ((st = kick(c, pend_s + 0.5 * dts, 0.0, dts))) return st;
             if ((st = do_build(c, true, false))) return st;
             if ((st = do_soft(c))) return st;
-            if ((st = kick(c, 0.5 * dts, 0.0, 0.0))) return st;
-            c->forces_current = true;
+            pend_s = 0.5 * dts;
             continue;
         }
         const int nsub = c->p.n_sub;
         const double dth = dts / nsub;
         for (int h = 0; h < nsub; h++) {
-            // opening kicks (soft half-kick on the first substep) and the drift
-            if ((st = kick(c, h == 0 ? 0.5 * dts : 0.0, 0.5 * dth, dth))) return st;
+            // opening kicks (soft half-kick on the first substep), the
+            // pending closing kicks, and the drift
+            if ((st = kick(c, pend_s + (h == 0 ? 0.5 * dts : 0.0), pend_h + 0.5 * dth, dth)))
+                return st;
             // a full build where the soft force needs it, a refit of the
             // node boxes on the other substeps
             const bool last = h == nsub - 1;
             if ((st = last ? do_build(c, true, false) : do_refit(c))) return st;
             if (last && (st = do_soft(c))) return st;
             if ((st = do_hard(c))) return st;
-            if ((st = kick(c, last ? 0.5 * dts : 0.0, 0.5 * dth, 0.0))) return st;
+            pend_s = last ? 0.5 * dts : 0.0;
+            pend_h = 0.5 * dth;
         }
-        c->forces_current = true;
     }
+    if (pend_s != 0.0 || pend_h != 0.0) {
+        if ((st = kick(c, pend_s, pend_h, 0.0))) return st;
+    }
+    c->forces_current = true;
     return HTREE_OK;
 }
 
