@@ -618,23 +618,37 @@ __device__ inline uint32_t cell_end(const uint64_t *key, int64_t p1, int64_t i, 
     return (uint32_t)hi;
 }
 
-__global__ __launch_bounds__(256) void k_emit_pre(const uint64_t *key, const int8_t *cpl,
-                                                  const uint32_t *nstart, int64_t n,
-                                                  const uint32_t *sys_of, const Sys *sys,
-                                                  int sysbits, uint32_t *pre_key,
-                                                  uint32_t *pre_val, uint32_t *pre_first,
-                                                  uint32_t *pre_count) {
+__global__ __launch_bounds__(256) void k_emit_pre(const int8_t *cpl, const uint32_t *nstart,
+                                                  int64_t n, const uint32_t *sys_of, int sysbits,
+                                                  uint32_t *pre_key, uint32_t *pre_val,
+                                                  uint32_t *pre_first) {
     int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     uint32_t p0 = nstart[i], p1 = nstart[i + 1];
     const uint32_t s = sys_of[i];
-    const int64_t end = sys[s].p1;
     int lev = cpl[i] + 1;
     for (uint32_t p = p0; p < p1; p++, lev++) {
         pre_key[p] = ((uint32_t)lev << sysbits) | s;
         pre_val[p] = p;
         pre_first[p] = (uint32_t)i;
-        pre_count[p] = cell_end(key, end, i, lev) - (uint32_t)i;
+    }
+}
+
+// Particle count of every pre-order node: the end of its cell in key order
+// (one thread per node, so the nodes that share a first particle -- the root
+// and its first descendants -- are searched side by side, not one after
+// another by that particle's thread).  Blocks stride over the nodes.
+__global__ __launch_bounds__(256) void k_node_count(const uint64_t *key, const uint32_t *pre_key,
+                                                    const uint32_t *pre_first, const uint32_t *nn,
+                                                    const Sys *sys, int sysbits,
+                                                    uint32_t *pre_count) {
+    const uint32_t n_nodes = *nn;
+    for (uint32_t p = blockIdx.x * 256 + threadIdx.x; p < n_nodes; p += gridDim.x * 256) {
+        const uint32_t k = pre_key[p];
+        const int lev = (int)(k >> sysbits);
+        const uint32_t s = k & ((1u << sysbits) - 1u);
+        const uint32_t i = pre_first[p];
+        pre_count[p] = cell_end(key, sys[s].p1, i, lev) - i;
     }
 }
 
@@ -1063,8 +1077,13 @@ void launch_topology(BuildBufs &B, bool moments, hipStream_t s) {
     hipLaunchKernelGGL(k_leaflev, dim3(gb), dim3(256), 0, s, B.cpl, dwin, n, B.sys_of, B.sys,
                        B.leaflev, B.nstart);
     launch_scan_u32(B.nstart, n + 1, B.scan_part, B.nn, s);
-    hipLaunchKernelGGL(k_emit_pre, dim3(gb), dim3(256), 0, s, key, B.cpl, B.nstart, n, B.sys_of,
-                       B.sys, B.sysbits, B.pre_key, B.pre_val, B.pre_first, B.pre_count);
+    hipLaunchKernelGGL(k_emit_pre, dim3(gb), dim3(256), 0, s, B.cpl, B.nstart, n, B.sys_of,
+                       B.sysbits, B.pre_key, B.pre_val, B.pre_first);
+    {
+        const int64_t nb = (B.nnmax + 255) / 256;
+        hipLaunchKernelGGL(k_node_count, dim3((unsigned)(nb < 2048 ? nb : 2048)), dim3(256), 0, s,
+                           key, B.pre_key, B.pre_first, B.nn, B.sys, B.sysbits, B.pre_count);
+    }
     // stable partition by (level, system): 5 + sysbits key bits
     const int kbits = 5 + B.sysbits;
     int64_t nb = sort_blocks(B.nnmax);
