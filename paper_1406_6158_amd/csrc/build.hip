@@ -85,10 +85,22 @@ __global__ __launch_bounds__(1024) void k_scan_partials(uint32_t *part, int64_t 
     if (threadIdx.x == 0 && total) *total = carry;
 }
 
+// SELF: the block adds up the block sums before its own (part[0, blockIdx.x))
+// instead of reading their prefix from k_scan_partials, and the last block
+// writes the grand total; used while the blocks are few.
+template <bool SELF>
 __global__ __launch_bounds__(kScanNT) void k_scan_down(uint32_t *data, int64_t n,
-                                                       const uint32_t *part) {
+                                                       const uint32_t *part, uint32_t *total) {
     __shared__ uint32_t sh[kScanNT / 64 + 1];
     int64_t base = (int64_t)blockIdx.x * kScanChunk;
+    uint32_t before = 0;
+    if (SELF) {
+        uint32_t p = 0;
+        for (uint32_t j = threadIdx.x; j < blockIdx.x; j += kScanNT) p += part[j];
+        block_excl_scan<kScanNT>(p, sh, before);
+    } else {
+        before = part[blockIdx.x];
+    }
     // each thread owns kScanItems consecutive elements
     uint32_t v[kScanItems];
     uint32_t s = 0;
@@ -99,20 +111,29 @@ __global__ __launch_bounds__(kScanNT) void k_scan_down(uint32_t *data, int64_t n
         s += v[k];
     }
     uint32_t tot;
-    uint32_t ex = block_excl_scan<kScanNT>(s, sh, tot) + part[blockIdx.x];
+    uint32_t ex = block_excl_scan<kScanNT>(s, sh, tot) + before;
     for (int k = 0; k < kScanItems; k++) {
         int64_t i = t0 + k;
         if (i < n) data[i] = ex;
         ex += v[k];
     }
+    if (SELF && total && threadIdx.x == 0 && blockIdx.x == gridDim.x - 1) *total = before + tot;
 }
+
+constexpr int64_t kScanSelfMax = 4096;   // blocks up to which k_scan_down sums the prefix itself
 
 void launch_scan_u32(uint32_t *data, int64_t n, uint32_t *part, uint32_t *total, hipStream_t s) {
     int64_t nb = (n + kScanChunk - 1) / kScanChunk;
     if (nb < 1) nb = 1;
     hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanNT), 0, s, data, n, part);
-    hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, nb, total);
-    hipLaunchKernelGGL(k_scan_down, dim3((unsigned)nb), dim3(kScanNT), 0, s, data, n, part);
+    if (nb <= kScanSelfMax) {
+        hipLaunchKernelGGL(k_scan_down<true>, dim3((unsigned)nb), dim3(kScanNT), 0, s, data, n,
+                           part, total);
+    } else {
+        hipLaunchKernelGGL(k_scan_partials, dim3(1), dim3(1024), 0, s, part, nb, total);
+        hipLaunchKernelGGL(k_scan_down<false>, dim3((unsigned)nb), dim3(kScanNT), 0, s, data, n,
+                           part, nullptr);
+    }
 }
 
 // ---------------------------------------------------------------------------
