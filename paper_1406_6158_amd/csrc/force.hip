@@ -699,30 +699,40 @@ struct LeafOrder {
     }
 };
 
-// Pair tests of this lane's sink against 64 staged candidates (or `cnt` < 64
-// when CNT == 0): bit s of the result is set iff candidate s lies strictly
-// inside R2 by the exact FP64 test.
+// Pair tests of this lane's sink against 64 staged candidates (unrolled), or
+// against `cnt` <= 64 of them in a counted loop when CNT == 0: bit s of the
+// result is set iff candidate s lies strictly inside R2 by the exact FP64
+// test.  The two 32-bit halves of the mask are built separately: with a
+// 64-bit shift and OR per candidate the compiler keeps ORing zeros into the
+// other half.
 template <int CNT>
 __device__ inline uint64_t pair_tests(const double4 *t, int cnt, double xi, double yi, double zi,
                                       double R2sq) {
-    uint64_t mask = 0;
+    uint32_t half[2] = {0u, 0u};
     if (CNT == 64) {
 #pragma unroll
-        for (int s = 0; s < 64; s++) {
-            const double4 q = t[s];
-            double dx = q.x - xi, dy = q.y - yi, dz = q.z - zi;
-            double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            mask |= (uint64_t)(r2 < R2sq) << s;
+        for (int h = 0; h < 2; h++) {
+#pragma unroll
+            for (int b = 0; b < 32; b++) {
+                const double4 q = t[32 * h + b];
+                double dx = q.x - xi, dy = q.y - yi, dz = q.z - zi;
+                double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                half[h] |= r2 < R2sq ? 1u << b : 0u;
+            }
         }
     } else {
-        for (int s = 0; s < cnt; s++) {
-            const double4 q = t[s];
-            double dx = q.x - xi, dy = q.y - yi, dz = q.z - zi;
-            double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
-            mask |= (uint64_t)(r2 < R2sq) << s;
+#pragma unroll
+        for (int h = 0; h < 2; h++) {
+            const int e = cnt - 32 * h < 32 ? cnt - 32 * h : 32;
+            for (int b = 0; b < e; b++) {
+                const double4 q = t[32 * h + b];
+                double dx = q.x - xi, dy = q.y - yi, dz = q.z - zi;
+                double r2 = fma(dz, dz, fma(dy, dy, dx * dx));
+                half[h] |= r2 < R2sq ? 1u << b : 0u;
+            }
         }
     }
-    return mask;
+    return (uint64_t)half[1] << 32 | half[0];
 }
 
 // 1/sqrt(s) in FP64: FP32 hardware seed (relative error about 1e-7), one
@@ -798,16 +808,19 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
     }
     __syncthreads();
 
-    // tests and accepted-pair forces for the top `cnt` (<= 128) staged candidates
-    auto eval_top = [&](int cnt) {
+    // tests and accepted-pair forces for the top `cnt` (<= 128) staged
+    // candidates: full stages of 128 (during the walk) with the unrolled
+    // tests, the rest (the final drain) with counted loops, whose code the
+    // compiler does not reorder into 64 live compare masks
+    auto eval_top = [&](int cnt, bool full) {
         const int base = nst - cnt;
         uint64_t m0, m1 = 0;
-        if (cnt >= 64) {
+        if (full) {
             m0 = pair_tests<64>(S.tq + base, 64, xi, yi, zi, R2sq);
-            if (cnt == 128) m1 = pair_tests<64>(S.tq + base + 64, 64, xi, yi, zi, R2sq);
-            else if (cnt > 64) m1 = pair_tests<0>(S.tq + base + 64, cnt - 64, xi, yi, zi, R2sq);
+            m1 = pair_tests<64>(S.tq + base + 64, 64, xi, yi, zi, R2sq);
         } else {
-            m0 = pair_tests<0>(S.tq + base, cnt, xi, yi, zi, R2sq);
+            m0 = pair_tests<0>(S.tq + base, cnt < 64 ? cnt : 64, xi, yi, zi, R2sq);
+            if (cnt > 64) m1 = pair_tests<0>(S.tq + base + 64, cnt - 64, xi, yi, zi, R2sq);
         }
         if (!act) m0 = m1 = 0;
         const uint32_t hits = (uint32_t)(__popcll(m0) + __popcll(m1));
@@ -881,7 +894,7 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
             if (pending) finish();
             pending = tot > 0;
             if (pending) issue(tot < 64u ? (int)tot : 64);
-            if (nst >= 128) eval_top(128);
+            if (nst >= 128) eval_top(128, true);
             if (!pending) break;
         }
         HT_CHECK(nr == 0);
@@ -958,7 +971,7 @@ __device__ void hard_group(const ForceArgs &A, HardLDS &S, uint32_t grp) {
         __syncthreads();
     }
     if (nl > 0) drain_batch();
-    while (nst > 0) eval_top(nst < 128 ? nst : 128);
+    while (nst > 0) eval_top(nst < 128 ? nst : 128, false);
 
     if (act) {
         const int64_t i = b0 + lane;
