@@ -264,6 +264,15 @@ int64_t htree_node_count(htree_ctx *ctx);
 htree_status htree_export_nodes(htree_ctx *ctx, int32_t *level, int32_t *first,
                                 int32_t *count, double *mass, double *com);
 
+/* Bounding boxes of the nodes' particles at the positions they were last
+ * computed for (the build, or htree_refit after a drift), in the order of
+ * htree_export_nodes: lo and hi are host arrays [3][nn] (either may be NULL)
+ * of the exact per-axis minima and maxima of the particles' FP64 positions.
+ * These are the boxes the hard search of section II.C tests against R2.
+ * ESTATE if they do not fit the current positions (a drift without a refit
+ * or a build).  Synchronises the stream. */
+htree_status htree_export_node_boxes(htree_ctx *ctx, double *lo, double *hi);
+
 const char *htree_last_error(void);
 
 /* Releases the host context; the caller then frees the workspace. */

@@ -216,6 +216,18 @@ class HTree:
                                                   ("level", "first", "count", "M", "com")]))
         return d
 
+    def export_node_boxes(self):
+        """(lo, hi) [3][nn] bounding boxes of the nodes' particles at the
+        positions of the last build or refit, in export_nodes order."""
+        import numpy as np
+        nn = int(lib().htree_node_count(self._h))
+        if nn < 0:
+            check(-3)
+        lo, hi = np.zeros((3, nn)), np.zeros((3, nn))
+        check(lib().htree_export_node_boxes(self._h, C.c_void_p(lo.ctypes.data),
+                                            C.c_void_p(hi.ctypes.data)))
+        return lo, hi
+
     def export_node_mac(self):
         """(B2, bmax2, rb2) of the last build's nodes, in export_nodes order."""
         import numpy as np

@@ -116,6 +116,7 @@ def lib() -> C.CDLL:
     L.htree_node_count.restype = C.c_int64
     L.htree_export_nodes.argtypes = [_p, _p, _p, _p, _p, _p]
     L.htree_export_node_mac.argtypes = [_p, _p, _p, _p]
+    L.htree_export_node_boxes.argtypes = [_p, _p, _p]
     L.htree_group_count.argtypes = [_p]
     L.htree_group_count.restype = C.c_int64
     L.htree_export_groups.argtypes = [_p, _p]
@@ -141,7 +142,8 @@ def lib() -> C.CDLL:
     for name in ("htree_create", "htree_create_static", "htree_batch_create", "htree_set_state", "htree_build_tree", "htree_soft_force",
                  "htree_hard_force", "htree_kick_drift", "htree_step", "htree_refit", "htree_get_state",
                  "htree_sync", "htree_stats", "htree_group_counts", "htree_export_keys",
-                 "htree_export_nodes", "htree_export_node_mac", "htree_export_groups"):
+                 "htree_export_nodes", "htree_export_node_mac", "htree_export_node_boxes",
+                 "htree_export_groups"):
         getattr(L, name).restype = _st
     _lib = L
     return L

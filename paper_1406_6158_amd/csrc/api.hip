@@ -900,6 +900,21 @@ htree_status htree_export_nodes(htree_ctx *c, int32_t *level, int32_t *first, in
     return HTREE_OK;
 }
 
+htree_status htree_export_node_boxes(htree_ctx *c, double *lo, double *hi) {
+    CTX_CHECK(c);
+    if (!c->topo || !c->boxes) return fail(HTREE_ESTATE, "no node boxes for the current positions");
+    int64_t nn = htree_node_count(c);
+    if (nn < 0) return fail(HTREE_EDEVICE, "cannot read the node count");
+    std::vector<double> h(8 * (nn > 0 ? nn : 1));
+    HIP_OK(hipMemcpy(h.data(), c->B.aabb, sizeof(double) * 8 * nn, hipMemcpyDeviceToHost));
+    for (int64_t k = 0; k < nn; k++)
+        for (int a = 0; a < 3; a++) {
+            if (lo) lo[a * nn + k] = h[8 * k + a];
+            if (hi) hi[a * nn + k] = h[8 * k + 4 + a];
+        }
+    return HTREE_OK;
+}
+
 htree_status htree_export_node_mac(htree_ctx *c, double *B2, double *bmax2, double *rb2) {
     CTX_CHECK(c);
     if (!c->tree) return fail(HTREE_ESTATE, "no current tree");

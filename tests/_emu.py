@@ -69,6 +69,11 @@ def lib():
         L.htree_group_count.argtypes = [_p]
         L.htree_group_count.restype = C.c_int64
         L.htree_export_groups.argtypes = [_p, _p]
+        L.htree_export_keys.argtypes = [_p, _p, _p, _p]
+        L.htree_node_count.argtypes = [_p]
+        L.htree_node_count.restype = C.c_int64
+        L.htree_export_nodes.argtypes = [_p, _p, _p, _p, _p, _p]
+        L.htree_export_node_boxes.argtypes = [_p, _p, _p]
         L.htree_last_error.restype = C.c_char_p
         L.htree_destroy.argtypes = [_p]
         _lib = L
@@ -127,6 +132,27 @@ class EmuTree:
 
     def refit(self):
         self._check(lib().htree_refit(self._h))
+
+    def perm(self):
+        """Sorted position -> caller index, of the last build."""
+        p = np.zeros(self.n, np.int32)
+        self._check(lib().htree_export_keys(self._h, None, _ptr(p), None))
+        return p
+
+    def node_ranges(self):
+        """(first, count) of every node, in level order."""
+        nn = lib().htree_node_count(self._h)
+        assert nn >= 0
+        first, count = np.zeros(nn, np.int32), np.zeros(nn, np.int32)
+        self._check(lib().htree_export_nodes(self._h, None, _ptr(first), _ptr(count), None, None))
+        return first, count
+
+    def node_boxes(self):
+        nn = lib().htree_node_count(self._h)
+        assert nn >= 0
+        lo, hi = np.zeros((3, nn)), np.zeros((3, nn))
+        self._check(lib().htree_export_node_boxes(self._h, _ptr(lo), _ptr(hi)))
+        return lo, hi
 
     def get_state(self):
         x = np.zeros((3, self.n), np.float64)

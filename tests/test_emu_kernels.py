@@ -117,6 +117,42 @@ def test_hard_search_replay_emulated(orc, emu, name):
         assert np.percentile(e, 99) <= TOL_P99
 
 
+def brute_boxes(xs, first, count):
+    """Per-axis minima and maxima of the sorted positions xs [3][n] over each
+    node's range [first, first + count), one node at a time."""
+    lo = np.empty((3, first.size))
+    hi = np.empty((3, first.size))
+    for k in range(first.size):
+        seg = xs[:, first[k]:first[k] + count[k]]
+        lo[:, k] = seg.min(axis=1)
+        hi[:, k] = seg.max(axis=1)
+    return lo, hi
+
+
+@pytest.mark.parametrize("name", ["plummer4k", "dups_lognormal"])
+def test_node_boxes_after_refits_emulated(emu, name):
+    """Node boxes after the build (level pass) and after each drift + refit
+    (chunk covers) equal, bit for bit, the minima and maxima of each node's
+    particles at the current positions; without the refit they are refused."""
+    x, v, m, eps, R1, R2, G = _case(name)
+    t = emu.EmuTree(x, v.astype(np.float32), m.astype(np.float32), G=G, eps=eps, R1=R1, R2=R2)
+    t.build_tree()
+    t.soft_force()
+    t.hard_force()          # the drift goes through the kick, which needs forces
+    perm = t.perm()
+    first, count = t.node_ranges()
+    for k in range(4):
+        if k:
+            t.kick_drift(0.0, 0.15)
+            with pytest.raises(RuntimeError):
+                t.node_boxes()
+            t.refit()
+        xd, _ = t.get_state()
+        lo, hi = t.node_boxes()
+        blo, bhi = brute_boxes(xd[:, perm], first, count)
+        assert np.array_equal(lo, blo) and np.array_equal(hi, bhi), k
+
+
 @pytest.mark.parametrize("name,hybrid,group_mac", [
     ("plummer4k", 1, 0), ("plummer4k", 1, 1), ("cube5000", 0, 1), ("dups_lognormal", 0, 1)])
 def test_soft_kernel_abs_mac_emulated(orc, emu, name, hybrid, group_mac):

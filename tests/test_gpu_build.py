@@ -92,3 +92,72 @@ def test_nonfinite_input_reported():
     with pytest.raises(P.HTreeError) as ei:
         t.sync()
     assert ei.value.code == P.HTREE_EINVAL
+
+
+def _brute_boxes(xs, first, count):
+    """Per-axis minima and maxima of the sorted positions xs [3][n] over each
+    node's range [first, first + count), one node at a time."""
+    lo = np.empty((3, first.size))
+    hi = np.empty((3, first.size))
+    for k in range(first.size):
+        seg = xs[:, first[k]:first[k] + count[k]]
+        lo[:, k] = seg.min(axis=1)
+        hi[:, k] = seg.max(axis=1)
+    return lo, hi
+
+
+def _boxes_through_refits(P, torch, x, v32, m32, nodes_of, **kw):
+    """Builds, then drifts three times with a refit after each drift; after
+    the build and after every refit the exported node boxes must equal the
+    exact minima and maxima of the nodes' particles (nodes_of picks which
+    nodes to check); between a drift and its refit they are refused."""
+    t = make_tree(P, torch, x, v32, m32, **kw)
+    t.build_tree()
+    t.soft_force()
+    t.hard_force()          # the drift goes through the kick, which needs forces
+    _, perm, _, _ = t.export_keys()
+    nd = t.export_nodes()
+    sel = nodes_of(nd["count"])
+    first, count = nd["first"][sel], nd["count"][sel]
+    for k in range(4):
+        if k:
+            t.kick_drift(0.0, dt_drift=0.15)
+            with pytest.raises(P.HTreeError):
+                t.export_node_boxes()
+            t.refit()
+        xd, _ = t.get_state()
+        t.sync()
+        lo, hi = t.export_node_boxes()
+        blo, bhi = _brute_boxes(xd.cpu().numpy()[:, perm], first, count)
+        assert np.array_equal(lo[:, sel], blo) and np.array_equal(hi[:, sel], bhi), k
+    t.close()
+
+
+@pytest.mark.parametrize("case", ["plummer4k", "dups", "hernquist20k"])
+def test_node_boxes_after_refits(case):
+    """Every node's box, from the level pass and from the chunk-cover refit."""
+    torch, P = need_gpu()
+    x, v, m = _case(case)
+    x, v32, m32, _, _ = as_inputs(x, v, m)
+    print("node boxes", case, flush=True)
+    _boxes_through_refits(P, torch, x, v32, m32, lambda c: np.arange(c.size),
+                          eps=0.01, R1=0.025, R2=0.05)
+
+
+def test_node_boxes_after_refits_2e20():
+    """At N = 2^20 (the refit's chunks of 32, 1024 and 32768 particles all in
+    use): every node above 1024 particles and 4096 sampled others."""
+    torch, P = need_gpu()
+    wl = synth.WORKLOADS["plummer1m"]
+    x, v, m = wl.make()
+    x, v32, m32, _, _ = as_inputs(x, v, m)
+    print("node boxes plummer 2^20", flush=True)
+    rng = np.random.default_rng(7)
+
+    def pick(count):
+        big = np.flatnonzero(count > 1024)
+        rest = rng.choice(np.flatnonzero(count <= 1024), 4096, replace=False)
+        return np.concatenate([big, rest])
+
+    _boxes_through_refits(P, torch, x, v32, m32, pick, eps=wl.eps, R1=wl.R1, R2=wl.R2,
+                          n_crit=wl.n_crit)
