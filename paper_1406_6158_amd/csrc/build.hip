@@ -955,31 +955,37 @@ __global__ __launch_bounds__(256) void k_box32(const double *x, const double *sr
         }
 }
 
+constexpr int kRefitLanes = 4;   // lanes per node in k_refit
+
 __global__ __launch_bounds__(256) void k_refit(const Node *node, const uint32_t *nn_dev,
                                                const uint32_t *pre2bfs, const double *x,
                                                int64_t n, const double *c1, int64_t m1,
                                                const double *c2, int64_t m2, const double *c3,
                                                int64_t m3, double *aabb, int64_t nnmax) {
-    // threads take nodes in pre-order, so neighbouring lanes hold leaves with
-    // adjacent particle ranges and their loads share cache lines
-    const uint32_t p = blockIdx.x * 256 + threadIdx.x;
+    // kRefitLanes consecutive lanes per node, nodes in pre-order, so
+    // neighbouring lanes hold leaves with adjacent particle ranges and their
+    // loads share cache lines; the node's lanes return together, so the
+    // shuffles below read only lanes that are still running
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t p = t / kRefitLanes, sub = t % kRefitLanes;
     if (p >= *nn_dev) return;
     const uint32_t b = pre2bfs[p];
     const uint32_t f = node[b].first, e = f + node[b].count;
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
     // [f, e) = singles | 32-chunks | 1024-chunks | 32768-chunks | 1024 | 32 | singles,
     // each run aligned to its chunk size (min and max are exact, so any cover
-    // gives the same box); every run is a counted loop whose loads are issued
-    // four at a time
-    auto run = [&](const double *t, int64_t m, uint32_t k0, uint32_t k1) {
-        for (uint32_t k = k0; k < k1; k += 4) {
+    // gives the same box); every run is a counted loop in which the node's
+    // lanes take every kRefitLanes-th piece, each lane four pieces at a time
+    constexpr uint32_t L = kRefitLanes;
+    auto run = [&](const double *c, int64_t m, uint32_t k0, uint32_t k1) {
+        for (uint32_t k = k0 + sub; k < k1; k += 4 * L) {
             double l4[4][3], h4[4][3];
 #pragma unroll
             for (int j = 0; j < 4; j++) {
-                const uint32_t kk = k + j < k1 ? k + j : k;
+                const uint32_t kk = k + j * L < k1 ? k + j * L : k;
                 for (int a = 0; a < 3; a++) {
-                    l4[j][a] = t[a * m + kk];
-                    h4[j][a] = t[(3 + a) * m + kk];
+                    l4[j][a] = c[a * m + kk];
+                    h4[j][a] = c[(3 + a) * m + kk];
                 }
             }
 #pragma unroll
@@ -991,11 +997,11 @@ __global__ __launch_bounds__(256) void k_refit(const Node *node, const uint32_t 
         }
     };
     auto singles = [&](uint32_t i0, uint32_t i1) {
-        for (uint32_t i = i0; i < i1; i += 4) {
+        for (uint32_t i = i0 + sub; i < i1; i += 4 * L) {
             double v4[4][3];
 #pragma unroll
             for (int j = 0; j < 4; j++) {
-                const uint32_t ii = i + j < i1 ? i + j : i;
+                const uint32_t ii = i + j * L < i1 ? i + j * L : i;
                 for (int a = 0; a < 3; a++) v4[j][a] = x[a * n + ii];
             }
 #pragma unroll
@@ -1029,7 +1035,12 @@ __global__ __launch_bounds__(256) void k_refit(const Node *node, const uint32_t 
             }
         }
     }
-    store_box(aabb, b, lo, hi);
+    for (int o = 1; o < (int)L; o <<= 1)
+        for (int a = 0; a < 3; a++) {
+            lo[a] = fmin(lo[a], __shfl_xor(lo[a], o));
+            hi[a] = fmax(hi[a], __shfl_xor(hi[a], o));
+        }
+    if (sub == 0) store_box(aabb, b, lo, hi);
 }
 
 // Sizes of the three chunk levels for n particles (entries of 6 doubles).
@@ -1051,8 +1062,9 @@ void launch_refit(BuildBufs &B, hipStream_t s) {
                        m1, c2, m2);
     hipLaunchKernelGGL(k_box32, dim3((unsigned)((m2 + 255) / 256)), dim3(256), 0, s, nullptr, c2,
                        m2, c3, m3);
-    hipLaunchKernelGGL(k_refit, dim3((unsigned)((B.nnmax + 255) / 256)), dim3(256), 0, s, B.node,
-                       B.nn, B.pre2bfs, x, n, c1, m1, c2, m2, c3, m3, B.aabb, B.nnmax);
+    hipLaunchKernelGGL(k_refit, dim3((unsigned)((kRefitLanes * B.nnmax + 255) / 256)), dim3(256),
+                       0, s, B.node, B.nn, B.pre2bfs, x, n, c1, m1, c2, m2, c3, m3, B.aabb,
+                       B.nnmax);
 }
 
 // The bottom-up pass over all levels (lstart must be current): node boxes,
