@@ -526,13 +526,31 @@ void launch_hard_order(BuildBufs &B, hipStream_t s) {
 // ---------------------------------------------------------------------------
 // permutation of the particle state into key order
 // ---------------------------------------------------------------------------
+// The dispatcher deals workgroups to the 8 XCDs round-robin (XCD = blockIdx %
+// 8), each XCD with its own L2.  With a grid of 8 * per blocks, block b takes
+// part (b % 8) * per + b / 8 (a bijection onto [0, 8 * per)), so each XCD
+// works through one contiguous eighth of the parts.
+constexpr uint32_t kXcds = 8;
+__device__ inline uint32_t xcd_part(uint32_t b, uint32_t grid) {
+    const uint32_t per = grid / kXcds;
+    return (b % kXcds) * per + b / kXcds;
+}
+inline unsigned xcd_grid(int64_t parts) {
+    const int64_t per = (parts + kXcds - 1) / kXcds;
+    return (unsigned)(kXcds * (per > 0 ? per : 1));
+}
+
+// Between two builds particles move by little in key order, so the rows a
+// block gathers lie in a window around its own positions that the
+// neighbouring blocks read too: the blocks run in XCD-contiguous order so
+// that those rows are fetched into one L2 rather than into all eight.
 template <bool ACC>
 __global__ __launch_bounds__(256) void k_gather(
     const uint32_t *idx, int64_t n, const uint32_t *sys_of, const Frame *frames, const double *x0,
     const float *v0, const float *m0, const uint32_t *p0, const float *as0, const float *ah0,
     const uint32_t *wc0, const uint32_t *wh0, double *x1, float *v1, float *m1, uint32_t *p1,
     float *as1, float *ah1, uint32_t *wc1, uint32_t *wh1, double4 *src, double4 *xm) {
-    int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    int64_t p = (int64_t)xcd_part(blockIdx.x, gridDim.x) * 256 + threadIdx.x;
     if (p >= n) return;
     uint32_t o = idx[p];
     const Frame &F = frames[sys_of[p]];
@@ -560,7 +578,7 @@ __global__ __launch_bounds__(256) void k_gather(
 void launch_gather(BuildBufs &B, bool keep_acc, hipStream_t s) {
     int c = B.cur, d = c ^ 1;
     int64_t n = B.n;
-    const dim3 grid((unsigned)((n + 255) / 256));
+    const dim3 grid(xcd_grid((n + 255) / 256));
     if (keep_acc)
         hipLaunchKernelGGL(k_gather<true>, grid, dim3(256), 0, s, B.idx[0], n, B.sys_of, B.frame,
                            B.x[c], B.v[c], B.m[c], B.perm[c], B.as[c], B.ah[c], B.wsoft[c],
