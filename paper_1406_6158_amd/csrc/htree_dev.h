@@ -170,9 +170,10 @@ __device__ inline uint32_t wave_max_u32(uint32_t v) {
 // Sticky device status bits.
 enum : uint32_t { kStatusNonFinite = 1u, kStatusOverflow = 2u };
 
-// Radix-sort tile: 256 threads x 16 items.
+// Radix-sort tile: 256 threads x 8 items (2048 keys; at N = 2^20, 512 tiles
+// keep two blocks on each CU through the scatter's barrier-separated rounds).
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;
+constexpr int kSortItems = 8;
 constexpr int kSortTile = kSortThreads * kSortItems;
 
 inline int64_t sort_blocks(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
