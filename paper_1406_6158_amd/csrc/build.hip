@@ -939,7 +939,7 @@ __global__ __launch_bounds__(256) void k_abs_mac(Node *node, const uint32_t *nn_
 // from their particle ranges, which needs no level order.  Boxes of aligned
 // chunks of 32, 32^2 and 32^3 sorted particles are reduced first; a node's
 // range is then covered by the largest aligned chunks that fit (at most 31
-// pieces of each size on either side), one lane per node, nodes in
+// pieces of each size on either side), kRefitLanes lanes per node, nodes in
 // pre-order.  Minima and maxima are exact, so the boxes equal those of the
 // level pass.
 constexpr int kC1 = 32;
