@@ -490,6 +490,10 @@ def main():
     ap.add_argument("--no-comparator", action="store_true")
     ap.add_argument("--ensemble-steps", type=int, default=8)
     ap.add_argument("--serve-requests", type=int, default=20000)
+    ap.add_argument("--paper-mac", action="store_true",
+                    help="time the same step with the paper's opening rule (absolute MAC, "
+                         "a_err = 2^-8, groups measured by their nearest sink) instead of "
+                         "theta = 0.5; the step line only (for kernel profiles of that rule)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run the reference kernels for scaling HBM byte counters and "
                          "exit: a plain 512 MiB device copy and a gather of 2^24 records of "
@@ -520,6 +524,10 @@ def main():
                           "gather_bytes_read": rows * 32 + rows * 8,
                           "gather_bytes_written": rows * 32, "launches": 5}))
         return
+    if args.paper_mac:
+        # the parity, ensemble, serving and comparator legs are defined for the
+        # theta rule
+        args.no_cpu_baseline = args.no_ensemble = args.no_serve = args.no_comparator = True
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the force path is single-GPU by design "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -538,9 +546,10 @@ def main():
     # the hard searches recorded after each build are replayed on the three
     # refitted substeps (exact neighbour sets; measured faster than walking
     # from the root every substep)
+    opening = dict(a_err=2.0 ** -8, group_mac=1) if args.paper_mac else {}
     params = P.default_params(eps=wl.eps, theta=wl.theta, R1=wl.R1, R2=wl.R2,
                               dt_soft=wl.dt_soft, n_sub=wl.n_sub, hybrid=1, n_crit=wl.n_crit,
-                              flags=P.F_TIMING | P.F_REUSE)
+                              flags=P.F_TIMING | P.F_REUSE, **opening)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     t = P.HTree(wl.n, params, device=dev)
@@ -588,6 +597,8 @@ def main():
     hflops = (FLOPS_HARD_TEST * st["hard_candidates"] + FLOPS_HARD_PAIR * st["hard_pairs"]) / hcalls
     hachieved = hflops / (hard_ms * 1e-3) / 1e12
     src_ok = _kernel_source_hash() == SOFT_TRAFFIC["source_hash"]
+    # the measured soft traffic is that of the theta-rule instance of the kernel
+    soft_ok = src_ok and not args.paper_mac
     line = {
         "metric": "interactions/s + s/step at N=2^20 Plummer; batched p50/p99 solve latency",
         "value": value,
@@ -603,9 +614,13 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "plummer N=2^20 eps=0.01 theta=0.5 ngb~64 n_sub=4 dt_h=1/64",
-                   "n": wl.n, "theta": wl.theta, "eps": wl.eps, "R2": wl.R2, "n_sub": wl.n_sub,
-                   "group": 64, "n_crit": wl.n_crit, "hard_search_reuse": True},
+        "config": {"workload": "plummer N=2^20 eps=0.01 %s ngb~64 n_sub=4 dt_h=1/64"
+                               % ("abs-MAC a_err=2^-8 nearest-sink" if args.paper_mac
+                                  else "theta=0.5"),
+                   "n": wl.n, "theta": None if args.paper_mac else wl.theta,
+                   "a_err": 2.0 ** -8 if args.paper_mac else None, "eps": wl.eps, "R2": wl.R2,
+                   "n_sub": wl.n_sub, "group": 64, "n_crit": wl.n_crit,
+                   "hard_search_reuse": True},
         "soft_interactions_per_step": soft_inter,
         "hard_pairs_per_step": hard_pairs,
         "hard_candidates_per_step": st["hard_candidates"] / K,
@@ -624,7 +639,7 @@ def main():
                                  "frac_of_packed_fp32_peak": achieved / PEAK_FP32_PACKED,
                                  "achieved_weight_within_R2_only": achieved_strict,
                                  "frac_weight_within_R2_only": achieved_strict / PEAK_FP32,
-                                 "traffic": SOFT_TRAFFIC["bytes"] if src_ok else None,
+                                 "traffic": SOFT_TRAFFIC["bytes"] if soft_ok else None,
                                  "traffic_unit": "bytes per launch (HBM, counter-measured)",
                                  "launch_ms": soft_ms, "share_of_step": st["ms_soft"] / K / ms_step},
         "cpu_baseline": None,
